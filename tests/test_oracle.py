@@ -1,0 +1,324 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each test checks the oracle against something other than itself: the plain
+definition of the partition problem evaluated by brute force in Python,
+Python's own sort, published SplitMix64 output values, a hand-worked example
+of the paper's line map (tests/golden/), and properties the paper proves for
+the Partial Partition Step.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+U64MAX = (1 << 64) - 1
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# SplitMix64 with state 0: its first three outputs, as published with the
+# generator's reference implementation (Vigna, prng.di.unimi.it, splitmix64.c).
+SPLITMIX64_SEED0 = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def _as(kind, vals):
+    if kind == "u32":
+        return np.array(vals, dtype=np.uint32)
+    if kind == "u64":
+        return np.array(vals, dtype=np.uint64)
+    a = np.zeros((len(vals), 2), dtype=np.uint64)
+    a[:, 0] = vals
+    a[:, 1] = np.arange(len(vals)) * 7 + 3
+    return a
+
+
+def _keys(a):
+    return [int(x) for x in (a[:, 0] if a.ndim == 2 else a)]
+
+
+def _records(a):
+    if a.ndim == 2:
+        return sorted((int(k), int(v)) for k, v in a)
+    return sorted(int(x) for x in a)
+
+
+# ----------------------------------------------------------------------------- generators
+
+def test_splitmix64_published_vectors():
+    assert [oracle.splitmix64(0, k) for k in range(3)] == SPLITMIX64_SEED0
+    assert [int(x) for x in workloads.splitmix64_np(0, 0, 3)] == SPLITMIX64_SEED0
+
+
+def test_workload_generator_counter_layout():
+    a = workloads.keys_u64(1000, 12345)
+    assert [int(x) for x in a[10:13]] == [int(x) for x in workloads.splitmix64_np(12345, 10, 3)]
+    assert np.array_equal(workloads.keys_u32(100, 7), (workloads.keys_u64(100, 7) >> np.uint64(32)).astype(np.uint32))
+    d = workloads.keys_few_distinct_u32(1 << 16, 3, 1024)
+    assert len(np.unique(d)) <= 1024 and len(np.unique(d)) > 1000
+
+
+def test_ss_offsets_pinned_to_stream():
+    # g = 2**31: multiply-shift of the top 32 bits reduces to dropping one more bit,
+    # so X_j must equal the published SplitMix64 outputs shifted right by 33.
+    X = oracle.ss_offsets(0, 0, 1 << 31, 3)
+    assert [int(x) for x in X] == [v >> 33 for v in SPLITMIX64_SEED0]
+
+
+def test_ss_offsets_range_and_uniformity():
+    for g in (1, 2, 3, 7, 1000, 131072):
+        X = oracle.ss_offsets(99, 2, g, 5000)
+        assert X.max() < g
+    assert not oracle.ss_offsets(5, 0, 1, 64).any()
+    g, s = 8, 80000
+    X = oracle.ss_offsets(2024, 1, g, s)
+    counts = np.bincount(X, minlength=g)
+    chi2 = float(((counts - s / g) ** 2 / (s / g)).sum())
+    assert chi2 < 40.0  # 7 dof; p < 1e-5 above this
+    # other levels and seeds give other offsets
+    assert not np.array_equal(X, oracle.ss_offsets(2024, 2, g, s))
+    assert not np.array_equal(X, oracle.ss_offsets(2025, 1, g, s))
+
+
+# ----------------------------------------------------------------------------- partition
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_partition_exhaustive_small(kind):
+    pivots = [0, 1, 2, 3, 4, U64MAX]
+    for n in range(0, 7):
+        for vals in itertools.product(range(4), repeat=n):
+            for p in pivots:
+                a = _as(kind, vals)
+                before = _records(a)
+                split = oracle.partition(a, p)
+                keys = _keys(a)
+                assert split == sum(1 for x in vals if x < p)
+                assert all(k < p for k in keys[:split]) and all(k >= p for k in keys[split:])
+                assert _records(a) == before
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_partition_all_pivots_n16(kind):
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(0, 17))
+        vals = [int(x) for x in rng.integers(0, 1 << 31, size=n)]
+        if trial % 3 == 0:
+            vals = [v % 5 for v in vals]
+        cands = sorted(set([0, 1, U64MAX] + vals + [v + 1 for v in vals]))
+        for p in cands:
+            a = _as(kind, vals)
+            split = oracle.partition(a, p)
+            assert split == sum(1 for x in vals if x < p) == oracle.count_less(_as(kind, vals), p)
+            assert oracle.is_partitioned(a, p, split)
+            assert sorted(_keys(a)[:split]) == sorted(x for x in vals if x < p)
+            assert sorted(_keys(a)[split:]) == sorted(x for x in vals if x >= p)
+
+
+def test_partition_large_against_numpy():
+    for kind, gen in (("u64", workloads.keys_u64), ("u32", workloads.keys_u32)):
+        a = gen(200_003, 77)
+        p = workloads.pivot_at_quantile_np(a, 0.3)
+        ref_l = np.sort(a[a < p]); ref_r = np.sort(a[a >= p])
+        split = oracle.partition(a, p)
+        assert split == len(ref_l) == workloads.quantile_rank(len(a), 0.3)
+        l, r = oracle.sorted_sides(a, split)
+        assert np.array_equal(l, ref_l) and np.array_equal(r, ref_r)
+
+
+def test_partition_le_decider():
+    a = np.array([3, 1, 2, 2, 5, 2, 0], dtype=np.uint64)
+    split = oracle.partition_le(a, 2)
+    assert split == 5 and all(int(x) <= 2 for x in a[:split]) and all(int(x) > 2 for x in a[split:])
+
+
+def test_u32_pivot_zero_extension():
+    a = np.array([0xFFFFFFFF, 0, 5], dtype=np.uint32)
+    assert oracle.count_less(a, 1 << 32) == 3
+    assert oracle.count_less(a, 0xFFFFFFFF) == 2
+
+
+def test_is_partitioned_detects_planted_mistakes():
+    a = workloads.keys_u64(5000, 3)
+    p = workloads.pivot_at_quantile_np(a, 0.5)
+    split = oracle.partition(a, p)
+    assert oracle.is_partitioned(a, p, split)
+    assert not oracle.is_partitioned(a, p, split + 1)
+    assert not oracle.is_partitioned(a, p, split - 1)
+    b = a.copy(); b[[0, -1]] = b[[-1, 0]]
+    assert not oracle.is_partitioned(b, p, split)
+
+
+# ----------------------------------------------------------------------------- quicksort
+
+@pytest.mark.parametrize("kind", ["u32", "u64"])
+def test_quicksort_matches_python_sort(kind):
+    rng = np.random.default_rng(5)
+    cases = [[], [1], [2, 1], list(range(100, 0, -1)), [7] * 50]
+    for n in (17, 31, 100, 1000, 4097):
+        cases.append([int(x) for x in rng.integers(0, 1 << 30, size=n)])
+        cases.append([int(x) for x in rng.integers(0, 4, size=n)])
+    for vals in cases:
+        a = _as(kind, vals)
+        oracle.quicksort(a)
+        assert _keys(a) == sorted(vals)
+        assert oracle.is_sorted(a)
+
+
+def test_quicksort_large_and_duplicates_against_numpy():
+    a = workloads.keys_u32(300_000, 9)
+    ref = np.sort(a)
+    oracle.quicksort(a)
+    assert np.array_equal(a, ref)
+    d = workloads.keys_few_distinct_u32(300_000, 9, 1024)
+    ref = np.sort(d)
+    oracle.quicksort(d)
+    assert np.array_equal(d, ref)
+
+
+def test_quicksort_kv_moves_payloads_with_keys():
+    a = workloads.records_kv(20_000, 4)
+    a[::3, 0] = a[: len(a[::3]), 0]  # plant repeated keys
+    before = _records(a)
+    oracle.quicksort(a)
+    assert _keys(a) == sorted(_keys(a))
+    assert _records(a) == before
+
+
+# ----------------------------------------------------------------------------- fingerprint
+
+def test_fingerprint_is_a_multiset_function():
+    a = workloads.keys_u64(10_000, 8)
+    f = oracle.fingerprint(a)
+    b = a[np.random.default_rng(1).permutation(len(a))].copy()
+    assert oracle.fingerprint(b) == f
+    c = a.copy(); c[17] ^= np.uint64(1)
+    assert oracle.fingerprint(c) != f
+    d = a.copy(); d[5] = d[6]
+    assert oracle.fingerprint(d) != f
+    kv = workloads.records_kv(1000, 2)
+    kv2 = kv.copy(); kv2[[3, 4], 1] = kv2[[4, 3], 1]  # same keys, payloads swapped between records
+    assert oracle.fingerprint(kv2) != oracle.fingerprint(kv)
+
+
+# ----------------------------------------------------------------------------- partial partition step
+
+def _geometry(n, b, g):
+    s = -(-n // (g * b))
+    return s
+
+
+def test_partial_step_line_map_golden():
+    with open(os.path.join(GOLDEN, "line_map_g3_s4_b2.txt")) as f:
+        rows = [list(map(int, ln.split())) for ln in f if ln.strip() and not ln.startswith("#")]
+    (g, s, b), X, groups = rows[0], rows[1], rows[2:]
+    n = g * s * b
+    owner = {}
+    first_line = {}
+    for i, lines in enumerate(groups):
+        first_line[i] = lines[0]
+        for ln in lines:
+            owner[ln] = i
+    assert sorted(owner) == list(range(g * s))
+    # One predecessor placed at the last element of line l moves to slot 0 of its
+    # group; the group is the one whose splitting position becomes slot 1.
+    for l in range(g * s):
+        a = np.full(n, 100, dtype=np.uint64)
+        a[l * b + b - 1] = 0
+        vmin, vmax, c, v = oracle.ss_partial_step(a, b, g, s, np.array(X), 50)
+        (i,) = [k for k in range(g) if c[k] == 1]
+        assert i == owner[l]
+        assert int(v[i]) == first_line[i] * b + 1
+        assert int(a[first_line[i] * b]) == 0
+        for k in range(g):
+            if k != i:
+                assert int(v[k]) == first_line[k] * b
+
+
+def _check_partial_step(a0, b, g, s, X, p):
+    a = a0.copy()
+    n = len(a)
+    vmin, vmax, c, v = oracle.ss_partial_step(a, b, g, s, X, p)
+    keys = a[:, 0] if a.ndim == 2 else a
+    # partially partitioned: everything before v_min is a predecessor, from v_max on a successor
+    assert (keys[:vmin] < p).all() and (keys[vmax:] >= p).all()
+    assert vmin <= vmax
+    # a permutation of the input
+    assert oracle.fingerprint(a) == oracle.fingerprint(a0)
+    # the group counts add up to the predecessor count
+    assert int(c.sum()) == oracle.count_less(a0, p)
+    # deterministic geometry of the proof of Proposition generalResult: |v_i - g c_i| < g b
+    gb = g * b
+    assert all(abs(int(v[i]) - g * int(c[i])) < gb for i in range(g))
+    return a, vmin, vmax, c, v
+
+
+def test_partial_step_single_group_is_full_partition():
+    for n, b in ((1, 1), (7, 2), (100, 16), (1000, 16), (4096, 16), (5000, 32)):
+        a0 = workloads.keys_u64(n, n + b)
+        p = workloads.pivot_at_quantile_np(a0, 0.4)
+        s = -(-n // b)
+        a, vmin, vmax, c, v = _check_partial_step(a0, b, 1, s, np.zeros(s, np.uint32), p)
+        assert vmin == vmax == oracle.count_less(a0, p)
+        assert oracle.is_partitioned(a, p, vmin)
+
+
+def test_partial_step_strided_groups_are_partitioned():
+    # X = 0: group i is P_i, the i-th line of every chunk (the Strided Algorithm).
+    n, b, g = 3000, 4, 25
+    s = _geometry(n, b, g)
+    a0 = workloads.keys_u64(n, 31)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    a, *_ = _check_partial_step(a0, b, g, s, np.zeros(s, np.uint32), p)
+    for i in range(g):
+        idx = [(j * g + i) * b + o for j in range(s) for o in range(b) if (j * g + i) * b + o < n]
+        before, after = a0[idx], a[idx]
+        assert sorted(before.tolist()) == sorted(after.tolist())
+        pred = (after < p).tolist()
+        assert pred == sorted(pred, reverse=True)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_partial_step_invariants_random(kind):
+    rng = np.random.default_rng(3)
+    for trial in range(30):
+        n = int(rng.integers(1, 5000))
+        b = int(rng.choice([1, 2, 4, 16]))
+        g = int(rng.integers(1, max(2, n // b)))
+        s = _geometry(n, b, g)
+        if (s - 1) * g * b >= n:
+            continue
+        if kind == "u32":
+            a0 = workloads.keys_u32(n, trial)
+        elif kind == "u64":
+            a0 = workloads.keys_u64(n, trial)
+        else:
+            a0 = workloads.records_kv(n, trial)
+        p = workloads.pivot_at_quantile_np(a0, float(rng.uniform(0, 1)))
+        X = oracle.ss_offsets(trial, 0, g, s)
+        _check_partial_step(a0, b, g, s, X, p)
+
+
+def test_partial_step_exhaustive_tiny():
+    # every offset vector for tiny geometries, 0/1 inputs
+    for n in range(1, 9):
+        for b in (1, 2):
+            for g in range(1, 5):
+                s = _geometry(n, b, g)
+                if (s - 1) * g * b >= n:
+                    continue
+                for X in itertools.product(range(g), repeat=s):
+                    for bits in range(1 << n):
+                        a0 = np.array([(bits >> k) & 1 for k in range(n)], dtype=np.uint64)
+                        _check_partial_step(a0, b, g, s, np.array(X, np.uint32), 1)
+
+
+def test_partial_step_rejects_bad_geometry():
+    a = np.zeros(100, np.uint64)
+    with pytest.raises(ValueError):
+        oracle.ss_partial_step(a, 4, 5, 3, np.zeros(3, np.uint32), 1)  # 60 < n
+    with pytest.raises(ValueError):
+        oracle.ss_partial_step(a, 4, 5, 6, np.zeros(6, np.uint32), 1)  # padding spans a chunk
+    with pytest.raises(ValueError):
+        oracle.ss_partial_step(a, 4, 5, 5, np.full(5, 5, np.uint32), 1)  # X_j >= g
