@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark: in-place partition of 2^30 uint64 keys on one MI355X.
+
+One step = one complete partition (every Partial Partition Step of the
+recursion, the final reduction and the split read back) of a fresh copy of
+the input, already resident in HBM.  The K timed steps use K distinct copies
+restored before the timed region, so every step sees the same i.i.d.
+workload.  `value` is the effective partition bandwidth 2 * n * 8 bytes per
+step over the wall time of the K steps (bracketed by device synchronization).
+
+The roofline object describes the dominant kernel (the first Partial
+Partition Step, which moves every element once): its algorithmic bytes
+2 * n * 8 over its average duration measured by HIP events that the library
+records on the launch stream, against the MI355X HBM peak of 8 TB/s.
+
+The CPU baseline is the serial oracle partition (single thread) on a bounded
+sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+WORKLOADS = {
+    # name: (dtype, log2 n, pivot quantile or "desc")
+    "partition_u64_2p30_q0.5": ("u64", 30, 0.5),
+    "partition_u64_2p30_q0.1": ("u64", 30, 0.1),
+    "partition_u64_2p30_q0.01": ("u64", 30, 0.01),
+    "partition_u64_2p30_desc": ("u64", 30, "desc"),
+}
+LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level.hip", "paper_2004_12532_amd/csrc/ss_device.h",
+                 "paper_2004_12532_amd/csrc/ss_common.h"]
+COUNTER_FILE = os.path.join(ROOT, "profiles", "level0_u64_2p30_counters.json")
+
+
+def level_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in LEVEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(n_bytes_alg: float):
+    """HBM bytes per launch of the first-level kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTER_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_digest") != level_source_digest():
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(seconds_budget: float = 12.0):
+    """Serial oracle partition on host copies of a 2^27-key sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    n = 1 << 27
+    a0 = workloads.keys_u64(n, workloads.config_seed(1))
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    work = np.empty_like(a0)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        np.copyto(work, a0)
+        t0 = time.perf_counter()
+        oracle.partition(work, p)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > seconds_budget or len(times) >= 20:
+            break
+    t = sorted(times)[len(times) // 2]
+    return {"value": round(2 * n * 8 / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "serial two-pointer partition of 2^27 i.i.d. uint64 keys (same generator) at the "
+                      "median, %d runs, median time %.3f s, 1 thread" % (len(times), t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="partition_u64_2p30_q0.5", choices=sorted(WORKLOADS))
+    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace"])
+    ap.add_argument("--b", type=int, default=0)
+    ap.add_argument("--tile-bytes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    if not 1 <= args.steps <= 24:
+        print("bench.py: --steps must be in [1, 24] (one 8 GiB input copy per timed step)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2004_12532_amd as ss
+    import workloads
+
+    torch.cuda.set_device(0)
+    dtype, log2n, q = WORKLOADS[args.workload]
+    n = 1 << log2n
+    w = 8
+    dev = torch.device("cuda", 0)
+
+    pristine = workloads.keys_u64_torch(n, workloads.config_seed(1), dev)
+    pivot = workloads.pivot_at_quantile_torch(pristine, 0.5 if q == "desc" else q)
+    if q == "desc":
+        pristine = workloads.sort_descending_u64_torch(pristine)
+    expected = int((workloads.to_unsigned_order(pristine) < workloads.to_unsigned_order(
+        torch.tensor([pivot - (1 << 64) if pivot >> 63 else pivot], dtype=torch.int64, device=dev))).sum().item())
+    bufs = [torch.empty_like(pristine) for _ in range(args.steps)]
+    kw = dict(algo=args.algo, b=args.b, tile_bytes=args.tile_bytes)
+
+    def restore(k):
+        bufs[k].copy_(pristine)
+
+    for k in range(args.steps):
+        restore(k)
+    for k in range(args.warmup):
+        ss.partition(bufs[k % args.steps], pivot, **kw)
+        restore(k % args.steps)
+    torch.cuda.synchronize()
+
+    level_ms, total_ms, splits, levels, stats = [], [], [], [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        split, st = ss.partition(bufs[k], pivot, stats=True, time=True, **kw)
+        splits.append(split)
+        level_ms.append(st["first_level_ms"])
+        total_ms.append(st["total_ms"])
+        stats = st
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ok = all(s == expected for s in splits)
+    alg_bytes = 2.0 * n * w
+    value = alg_bytes * args.steps / wall / 1e9
+    mean_level_ms = sum(level_ms) / len(level_ms)
+    achieved = alg_bytes / (mean_level_ms / 1e3) / 1e9
+
+    probe = None
+    if not args.no_probe:
+        ms_rw = min(ss.probe_bandwidth(bufs[0], 1) for _ in range(3))
+        ms_r = min(ss.probe_bandwidth(bufs[0], 0) for _ in range(3))
+        probe = {"rw_GBps": round(alg_bytes / ms_rw / 1e6, 1), "read_GBps": round(n * w / ms_r / 1e6, 1)}
+    del bufs
+    torch.cuda.empty_cache()
+
+    traffic = counter_traffic(alg_bytes)
+    out = {
+        "metric": "partition GB/s & % HBM peak, 2^30 u64; batched vs per-array launch; p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "n": n,
+            "pivot_quantile": q,
+            "algo": args.algo,
+            "b": stats["b"],
+            "s_max": stats["s_max"],
+            "grid": stats["grid"],
+            "parallelism": "single GPU",
+        },
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
+        "elements_per_s": round(n * args.steps / wall, 1),
+        "splits_correct": ok,
+        "levels": stats["levels"],
+        "level_sizes": [hi - lo for lo, hi in zip(stats["level_lo"], stats["level_hi"])],
+        "first_level_ms": round(mean_level_ms, 4),
+        "call_ms_device": round(sum(total_ms) / len(total_ms), 4),
+        "aux_bytes": stats["aux_bytes"],
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel": "k_level<uint64_t,256,65536,first> (first Partial Partition Step)",
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "probe": probe,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    if not ok:
+        print("bench.py: split mismatch %s vs expected %d" % (splits, expected), file=sys.stderr)
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

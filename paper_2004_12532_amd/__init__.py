@@ -1,0 +1,206 @@
+"""Python binding of libss.so: argument marshalling only.
+
+Every call goes through the C ABI declared in include/ss.h; all work runs in
+the library's HIP kernels.  PyTorch is used for device memory and streams:
+
+* SS_U32 arrays are int32 CUDA tensors (bit patterns read as uint32),
+* SS_U64 arrays are int64 CUDA tensors (bit patterns read as uint64),
+* SS_KV16 arrays are int64 CUDA tensors of shape (n, 2): key, payload.
+
+There is no fallback: if libss.so is missing, importing this package fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+# PyTorch ships its own HIP runtime under the same soname as ROCm's.  Loading
+# torch first makes libss.so bind to that already-loaded runtime, so the
+# process has one HIP runtime whichever package the caller imports first.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libss.so")
+if not os.path.exists(_SO):
+    raise ImportError("libss.so is not built; run `python paper_2004_12532_amd/build.py` "
+                      "(or __graft_entry__.build())")
+_lib = ctypes.CDLL(_SO)
+
+SS_U32, SS_U64, SS_KV16 = 1, 2, 3
+SMOOTHED, STRIDED, LOWSPACE = 0, 1, 2
+ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE}
+FLAG_ONE_LEVEL, FLAG_TIME = 1, 2
+MAX_LEVELS = 32
+STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",
+          -5: "SS_EINCOMPLETE"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("b", ctypes.c_uint32), ("tile_bytes", ctypes.c_uint32),
+                ("max_levels", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_uint64), ("aux_bytes", ctypes.c_uint64), ("lds_bytes", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32), ("b", ctypes.c_uint32), ("s_max", ctypes.c_uint32),
+                ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
+                ("level_lo", ctypes.c_uint64 * MAX_LEVELS), ("level_hi", ctypes.c_uint64 * MAX_LEVELS),
+                ("level_g", ctypes.c_uint32 * MAX_LEVELS), ("level_s", ctypes.c_uint32 * MAX_LEVELS),
+                ("vmin", ctypes.c_uint64), ("vmax", ctypes.c_uint64),
+                ("first_level_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+                ("bytes_moved", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        nl = self.levels
+        return {
+            "split": self.split, "aux_bytes": self.aux_bytes, "lds_bytes": self.lds_bytes, "grid": self.grid,
+            "b": self.b, "s_max": self.s_max, "levels": nl, "launches": self.launches,
+            "level_lo": list(self.level_lo[:nl]), "level_hi": list(self.level_hi[:nl]),
+            "level_g": list(self.level_g[:nl]), "level_s": list(self.level_s[:nl]),
+            "vmin": self.vmin, "vmax": self.vmax, "first_level_ms": self.first_level_ms,
+            "total_ms": self.total_ms, "bytes_moved": self.bytes_moved,
+        }
+
+
+_vp, _sz, _u64, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
+_lib.ss_partition.argtypes = [_vp, _sz, _int, _u64, ctypes.POINTER(_sz)]
+_lib.ss_partition_ex.argtypes = [_vp, _sz, _int, _u64, ctypes.POINTER(Params), _vp, _vp, ctypes.POINTER(_sz),
+                                 ctypes.POINTER(Stats)]
+_lib.ss_quicksort.argtypes = [_vp, _sz, _int]
+_lib.ss_quicksort_ex.argtypes = [_vp, _sz, _int, ctypes.POINTER(Params), _vp, ctypes.POINTER(Stats)]
+_lib.ss_partition_batched.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp,
+                                      ctypes.POINTER(Stats)]
+_lib.ss_aux_bytes.argtypes = [_sz, _int, _int]
+_lib.ss_aux_bytes.restype = _sz
+_lib.ss_strerror.argtypes = [_int]
+_lib.ss_strerror.restype = ctypes.c_char_p
+_lib.ss_last_error.argtypes = []
+_lib.ss_last_error.restype = ctypes.c_char_p
+_lib.ss_probe_bandwidth.argtypes = [_vp, _sz, _int, _vp, ctypes.POINTER(ctypes.c_float)]
+_lib.ss_device_info.argtypes = [ctypes.POINTER(_int)] * 4
+for _f in ("ss_partition", "ss_partition_ex", "ss_quicksort", "ss_quicksort_ex", "ss_partition_batched",
+           "ss_probe_bandwidth", "ss_device_info"):
+    getattr(_lib, _f).restype = _int
+
+LIB_PATH = _SO
+lib = _lib
+
+
+class SSError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        detail = _lib.ss_last_error().decode()
+        super().__init__("%s failed: %s (%s)%s" % (what, STATUS.get(code, code), _lib.ss_strerror(code).decode(),
+                                                   (": " + detail) if detail else ""))
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise SSError(code, what)
+
+
+def dtype_of(t) -> int:
+    """ss_dtype of a tensor: int32[n] -> U32, int64[n] -> U64, int64[n,2] -> KV16."""
+    import torch
+    if t.dim() == 1 and t.dtype in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        return SS_U32
+    if t.dim() == 1 and t.dtype in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        return SS_U64
+    if t.dim() == 2 and t.shape[1] == 2 and t.dtype in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        return SS_KV16
+    raise TypeError("expected int32[n], int64[n] or int64[n,2], got %s%s" % (t.dtype, tuple(t.shape)))
+
+
+def _array(t):
+    if not t.is_cuda:
+        raise ValueError("the array must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("the array must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()), t.shape[0], dtype_of(t)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False) -> Params:
+    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0)
+    return Params(a, b, tile_bytes, max_levels, seed, flags, 0)
+
+
+def partition(t, pivot: int, *, stats: bool = False, stream=None, **kw):
+    """Partition the tensor in place by key < pivot; returns the split (and the stats dict)."""
+    ptr, n, dt = _array(t)
+    p = make_params(**kw)
+    split = _sz(0)
+    st = Stats()
+    _check(_lib.ss_partition_ex(ptr, n, dt, pivot & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), None,
+                                ctypes.byref(split), ctypes.byref(st) if stats else None), "ss_partition_ex")
+    return (split.value, st.as_dict()) if stats else split.value
+
+
+def partition_async(t, pivot: int, d_split, *, stream=None, **kw) -> None:
+    """Partition without synchronizing; the split lands in d_split[0] (an int64 CUDA tensor)."""
+    ptr, n, dt = _array(t)
+    p = make_params(**kw)
+    _check(_lib.ss_partition_ex(ptr, n, dt, pivot & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
+                                ctypes.c_void_p(d_split.data_ptr()), None, None), "ss_partition_ex")
+
+
+def partition_plain(t, pivot: int) -> int:
+    """ss_partition: default parameters, default stream, blocking."""
+    ptr, n, dt = _array(t)
+    split = _sz(0)
+    _check(_lib.ss_partition(ptr, n, dt, pivot & ((1 << 64) - 1), ctypes.byref(split)), "ss_partition")
+    return split.value
+
+
+def quicksort(t, *, stats: bool = False, stream=None, **kw):
+    """Sort the tensor in place ascending by (unsigned) key."""
+    ptr, n, dt = _array(t)
+    p = make_params(**kw)
+    st = Stats()
+    _check(_lib.ss_quicksort_ex(ptr, n, dt, ctypes.byref(p), _stream(stream), ctypes.byref(st) if stats else None),
+           "ss_quicksort_ex")
+    return st.as_dict() if stats else None
+
+
+def partition_batched(base, offsets, pivots, splits, *, stats: bool = False, stream=None, **kw):
+    """Partition base[offsets[k]:offsets[k+1]] by pivots[k] for every k.
+
+    offsets: host sequence of num+1 element offsets; pivots, splits: int64 CUDA tensors of num entries."""
+    import numpy as np
+    ptr, _, dt = _array(base)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    num = len(off) - 1
+    p = make_params(**kw)
+    st = Stats()
+    _check(_lib.ss_partition_batched(ptr, ctypes.c_void_p(off.ctypes.data), num, dt,
+                                     ctypes.c_void_p(pivots.data_ptr()), ctypes.c_void_p(splits.data_ptr()),
+                                     ctypes.byref(p), _stream(stream), ctypes.byref(st) if stats else None),
+           "ss_partition_batched")
+    return st.as_dict() if stats else None
+
+
+def aux_bytes(n: int, dtype: int, algo="smoothed") -> int:
+    return _lib.ss_aux_bytes(n, dtype, ALGOS[algo] if isinstance(algo, str) else int(algo))
+
+
+def probe_bandwidth(t, mode: int, stream=None) -> float:
+    """Duration in ms of the read (mode 0) or read/overwrite (mode 1) probe over the tensor's bytes."""
+    ms = ctypes.c_float(0)
+    nbytes = t.numel() * t.element_size()
+    _check(_lib.ss_probe_bandwidth(ctypes.c_void_p(t.data_ptr()), nbytes, mode, _stream(stream),
+                                   ctypes.byref(ms)), "ss_probe_bandwidth")
+    return ms.value
+
+
+def device_info() -> dict:
+    v = [_int(0) for _ in range(4)]
+    _check(_lib.ss_device_info(*[ctypes.byref(x) for x in v]), "ss_device_info")
+    return {"compute_units": v[0].value, "lds_per_block": v[1].value, "major": v[2].value, "minor": v[3].value}

@@ -1,0 +1,503 @@
+// ss_api.cpp -- host driver and C ABI (include/ss.h).
+//
+// Responsibilities: argument validation (before any device work), the
+// per-(device, stream) workspace, the choice of kernel variant and grid, the
+// chain of Partial Partition Step launches of the recursion (Section 4,
+// Recursive Smoothed Striding), continuing the recursion from the host when
+// the device-side level budget runs out, and the per-call statistics.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "ss.h"
+#include "ss_common.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+thread_local std::string t_last_error;
+
+int fail_device(hipError_t e, const char *what)
+{
+    t_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SS_EDEVICE;
+}
+
+int fail_msg(int code, const std::string &msg)
+{
+    t_last_error = msg;
+    return code;
+}
+
+namespace {
+
+std::mutex g_mu;
+
+struct DevInfo {
+    int cus = 0;
+    int lds = 0;
+    int major = 0, minor = 0;
+    std::map<const void *, int> occupancy;
+};
+std::map<int, DevInfo> g_dev;
+std::map<std::pair<int, void *>, Workspace> g_ws;
+
+}  // namespace
+
+int device_info(int dev, int *cus, int *lds)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) {
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess)
+            return fail_device(e, "hipGetDeviceProperties");
+        DevInfo d;
+        d.cus = prop.multiProcessorCount;
+        d.lds = (int)prop.sharedMemPerBlock;
+        d.major = prop.major;
+        d.minor = prop.minor;
+        it = g_dev.emplace(dev, d).first;
+    }
+    *cus = it->second.cus;
+    *lds = it->second.lds;
+    return SS_OK;
+}
+
+int occupancy(int dev, const void *fn, int nt, int *blocks)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevInfo &d = g_dev[dev];
+    auto it = d.occupancy.find(fn);
+    if (it != d.occupancy.end()) {
+        *blocks = it->second;
+        return SS_OK;
+    }
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, 0);
+    if (e != hipSuccess)
+        return fail_device(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (nb < 1)
+        nb = 1;
+    d.occupancy[fn] = nb;
+    *blocks = nb;
+    return SS_OK;
+}
+
+int get_workspace(int dev, void *stream, Workspace **out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = &it->second;
+        return SS_OK;
+    }
+    Workspace w;
+    w.part_words = (size_t)kMaxLevels * 2 * kMaxGrid;
+    w.ctl_words = (size_t)kMaxLevels * kCtlWords;
+    const size_t words = w.part_words + w.ctl_words + kResultWords;
+    hipError_t e = hipMalloc((void **)&w.part, words * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail_msg(SS_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+    }
+    w.ctl = w.part + w.part_words;
+    w.result = w.ctl + w.ctl_words;
+    e = hipHostMalloc((void **)&w.host, (w.ctl_words + kResultWords) * sizeof(uint64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(w.part);
+        (void)hipGetLastError();
+        return fail_msg(SS_ENOMEM, std::string("workspace hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < 4; k++) {
+        e = hipEventCreate(&w.ev[k]);
+        if (e != hipSuccess)
+            return fail_device(e, "hipEventCreate");
+    }
+    w.bytes = words * sizeof(uint64_t);
+    it = g_ws.emplace(key, w).first;
+    *out = &it->second;
+    return SS_OK;
+}
+
+int elem_size(int dtype)
+{
+    switch (dtype) {
+    case SS_U32: return 4;
+    case SS_U64: return 8;
+    case SS_KV16: return 16;
+    default: return 0;
+    }
+}
+
+int ilog2(uint64_t x)
+{
+    int r = 0;
+    while ((1ull << r) < x)
+        r++;
+    return r;
+}
+
+// Resolve defaults and validate parameters (no device work).
+int resolve_params(const ss_params *p, int dtype, Resolved *r)
+{
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    ss_params q;
+    std::memset(&q, 0, sizeof(q));
+    if (p)
+        q = *p;
+    if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE)
+        return fail_msg(SS_EINVAL, "unknown algo");
+    if (q.reserved != 0 || (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME)))
+        return fail_msg(SS_EINVAL, "unknown flags or nonzero reserved field");
+    const uint32_t tile = q.tile_bytes ? q.tile_bytes : 65536u;
+    if (tile != 32768u && tile != 65536u)
+        return fail_msg(SS_EINVAL, "tile_bytes must be 32768 or 65536");
+    const uint32_t b = q.b ? q.b : 128u / w;
+    const uint64_t line = (uint64_t)b * w;
+    if (b == 0 || (b & (b - 1)) || line < 64 || line > 4096 || line > tile)
+        return fail_msg(SS_EINVAL, "b * sizeof(element) must be a power of two in [64, 4096] bytes");
+    const uint32_t levels = q.max_levels ? q.max_levels : 10u;
+    if (levels > (uint32_t)kMaxLevels)
+        return fail_msg(SS_EINVAL, "max_levels above 32");
+    r->algo = q.algo;
+    r->w = w;
+    r->b = b;
+    r->log2b = ilog2(b);
+    r->tile = tile;
+    r->s_max = (uint32_t)(tile / line);
+    r->levels = levels;
+    r->seed = q.seed ? q.seed : 0x5EEDC0DE2004ull;
+    r->flags = q.flags;
+    return SS_OK;
+}
+
+const Variant *pick_variant(int dtype, uint32_t tile)
+{
+    static const Variant v[] = {
+        {SS_U32, 65536, 256, &launch_level<uint32_t, 256, 65536>, &level_fn<uint32_t, 256, 65536>},
+        {SS_U64, 65536, 256, &launch_level<uint64_t, 256, 65536>, &level_fn<uint64_t, 256, 65536>},
+        {SS_KV16, 65536, 256, &launch_level<KV, 256, 65536>, &level_fn<KV, 256, 65536>},
+        {SS_U32, 32768, 256, &launch_level<uint32_t, 256, 32768>, &level_fn<uint32_t, 256, 32768>},
+        {SS_U64, 32768, 256, &launch_level<uint64_t, 256, 32768>, &level_fn<uint64_t, 256, 32768>},
+        {SS_KV16, 32768, 256, &launch_level<KV, 256, 32768>, &level_fn<KV, 256, 32768>},
+    };
+    for (const Variant &x : v)
+        if (x.dtype == dtype && x.tile == tile)
+            return &x;
+    return nullptr;
+}
+
+int check_array(const void *d_ptr, size_t n, int dtype)
+{
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    if (n > 0 && !d_ptr)
+        return fail_msg(SS_EINVAL, "null array pointer with n > 0");
+    const uintptr_t align = w == 16 ? 16 : (uintptr_t)w;
+    if ((uintptr_t)d_ptr % align)
+        return fail_msg(SS_EINVAL, "array pointer not aligned to its element size");
+    if (n > (size_t)1 << 40)
+        return fail_msg(SS_EINVAL, "n above 2^40");
+    return SS_OK;
+}
+
+// Run the recursion of Smoothed Striding (or the single Strided step) on
+// [lo0, hi0) of the array.  Writes the result record to ws->result and the
+// split to d_split.  When `sync` the host finishes the recursion if the
+// device budget runs out and fills *host_out.
+int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                  uint64_t *d_split, bool sync, RunOut *ro)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    int cus = 0, lds = 0;
+    int rc = device_info(dev, &cus, &lds);
+    if (rc)
+        return rc;
+    Workspace *ws = nullptr;
+    rc = get_workspace(dev, st, &ws);
+    if (rc)
+        return rc;
+    const Variant *V = pick_variant(dtype, R.tile);
+    if (!V)
+        return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
+    int occ = 0;
+    rc = occupancy(dev, V->fn(true), V->nt, &occ);
+    if (rc)
+        return rc;
+    uint32_t P = (uint32_t)(occ * cus);
+    if (P > (uint32_t)kMaxGrid)
+        P = kMaxGrid;
+    ro->grid = P;
+    ro->aux_bytes = ws->bytes;
+    ro->launches = 0;
+
+    const bool timing = (R.flags & SS_FLAG_TIME) != 0;
+    const bool strided = R.algo == SS_STRIDED;
+    const uint32_t budget = (R.flags & SS_FLAG_ONE_LEVEL) || strided ? 1u : R.levels;
+
+    uint64_t lo = 0, hi = n;
+    uint32_t level = 0;  // global level index (fresh offsets per level)
+    ro->levels_run = 0;
+    for (;;) {
+        LevelArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.base = base;
+        a.n = n;
+        a.pivot = pivot;
+        a.seed = R.seed;
+        a.log2b = R.log2b;
+        a.s_max = R.s_max;
+        a.strided = strided ? 1u : 0u;
+        uint32_t prev_count = 0;
+        const uint64_t *prev = nullptr;
+        for (uint32_t k = 0; k < budget; k++, level++) {
+            const bool first = k == 0;
+            uint32_t grid = P;
+            if (first) {
+                const Geo G = plan_geo((uintptr_t)base, lo, hi, R.w, R.log2b, R.s_max);
+                grid = G.g < P ? G.g : P;
+                a.lo = lo;
+                a.hi = hi;
+            }
+            a.level = level;
+            a.prev = prev;
+            a.prev_count = prev_count;
+            a.out = ws->part + (size_t)(level % kMaxLevels) * 2 * kMaxGrid;
+            a.ctl = ws->ctl + (size_t)(level % kMaxLevels) * kCtlWords;
+            if (timing && level == 0) {
+                if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
+                    return fail_device(e, "hipEventRecord");
+            }
+            if ((e = V->launch(first, grid, a, st)) != hipSuccess)
+                return fail_device(e, "level kernel launch");
+            ro->launches++;
+            if (timing && level == 0) {
+                if ((e = hipEventRecord(ws->ev[1], st)) != hipSuccess)
+                    return fail_device(e, "hipEventRecord");
+            }
+            prev = a.out;
+            prev_count = grid;
+        }
+        if (strided && !(R.flags & SS_FLAG_ONE_LEVEL)) {
+            // Serial Cleanup Step: one workgroup partitions [v_min, v_max).
+            if ((e = launch_cleanup(dtype, base, pivot, prev, prev_count, ws->result, d_split, st)) !=
+                hipSuccess)
+                return fail_device(e, "cleanup kernel launch");
+            ro->launches++;
+        } else {
+            if ((e = launch_finish(prev, prev_count, ws->result, d_split, st)) != hipSuccess)
+                return fail_device(e, "finish kernel launch");
+            ro->launches++;
+        }
+        ro->levels_run = level;
+        if (!sync)
+            return SS_OK;
+        e = hipMemcpyAsync(ws->host, ws->ctl, (ws->ctl_words + kResultWords) * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess)
+            return fail_device(e, "hipMemcpyAsync");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return fail_device(e, "hipStreamSynchronize");
+        const uint64_t *res = ws->host + ws->ctl_words;
+        // level records of this round
+        for (uint32_t l = level - budget; l < level; l++) {
+            if (l >= (uint32_t)SS_MAX_LEVELS)
+                break;
+            const uint64_t *c = ws->host + (size_t)(l % kMaxLevels) * kCtlWords;
+            ro->level_lo[l] = c[0];
+            ro->level_hi[l] = c[1];
+            ro->level_g[l] = (uint32_t)c[2];
+            ro->level_s[l] = (uint32_t)c[3];
+        }
+        ro->vmin = res[2];
+        ro->vmax = res[3];
+        if (res[0] || (R.flags & SS_FLAG_ONE_LEVEL)) {
+            ro->done = res[0] != 0;
+            ro->split = res[1];
+            break;
+        }
+        if (level >= kHostLevelCap)
+            return fail_msg(SS_EDEVICE, "recursion did not converge");
+        lo = res[2];
+        hi = res[3];
+    }
+    if (timing) {
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, ws->ev[0], ws->ev[1])) != hipSuccess)
+            return fail_device(e, "hipEventElapsedTime");
+        ro->first_level_ms = ms;
+    }
+    return SS_OK;
+}
+
+void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype)
+{
+    std::memset(st, 0, sizeof(*st));
+    st->split = ro.split;
+    st->aux_bytes = ro.aux_bytes;
+    st->grid = ro.grid;
+    st->b = R.b;
+    st->s_max = R.s_max;
+    st->launches = ro.launches;
+    st->vmin = ro.vmin;
+    st->vmax = ro.vmax;
+    st->first_level_ms = ro.first_level_ms;
+    st->total_ms = ro.total_ms;
+    st->lds_bytes = R.tile + R.tile / 64 * 4 + 1024;
+    uint64_t moved = 0;
+    uint32_t lv = 0;
+    for (uint32_t l = 0; l < ro.levels_run && l < (uint32_t)SS_MAX_LEVELS; l++) {
+        if (ro.level_hi[l] > ro.level_lo[l]) {
+            st->level_lo[lv] = ro.level_lo[l];
+            st->level_hi[lv] = ro.level_hi[l];
+            st->level_g[lv] = ro.level_g[l];
+            st->level_s[lv] = ro.level_s[l];
+            moved += 2ull * elem_size(dtype) * (ro.level_hi[l] - ro.level_lo[l]);
+            lv++;
+        }
+    }
+    st->levels = lv;
+    st->bytes_moved = moved;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_params *p, void *stream,
+                    uint64_t *d_split, size_t *h_split, ss_stats *stats)
+{
+    int rc = check_array(d_ptr, n, dtype);
+    if (rc)
+        return rc;
+    Resolved R;
+    rc = resolve_params(p, dtype, &R);
+    if (rc)
+        return rc;
+    if (R.algo == SS_LOWSPACE)
+        return lowspace_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split,
+                                  stats);
+    if (d_split && ((uintptr_t)d_split % 8))
+        return fail_msg(SS_EINVAL, "d_split not 8-byte aligned");
+    const bool sync = h_split || stats;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        if (d_split) {
+            hipError_t e = hipMemsetAsync(d_split, 0, sizeof(uint64_t), st);
+            if (e != hipSuccess)
+                return fail_device(e, "hipMemsetAsync");
+        }
+        if (sync) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e != hipSuccess)
+                return fail_device(e, "hipStreamSynchronize");
+        }
+        if (h_split)
+            *h_split = 0;
+        if (stats) {
+            RunOut ro;
+            std::memset(&ro, 0, sizeof(ro));
+            fill_stats(stats, ro, R, dtype);
+        }
+        return SS_OK;
+    }
+    RunOut ro;
+    std::memset(&ro, 0, sizeof(ro));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    const bool timing = (R.flags & SS_FLAG_TIME) != 0;
+    if (timing) {
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+            return fail_msg(SS_EDEVICE, "hipEventCreate");
+        (void)hipEventRecord(t0, st);
+    }
+    rc = run_partition((char *)d_ptr, n, dtype, pivot, R, st, d_split, sync || timing, &ro);
+    if (timing) {
+        (void)hipEventRecord(t1, st);
+        (void)hipEventSynchronize(t1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ro.total_ms = ms;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    }
+    if (rc)
+        return rc;
+    if (h_split)
+        *h_split = (size_t)ro.split;
+    if (stats)
+        fill_stats(stats, ro, R, dtype);
+    return SS_OK;
+}
+
+int ss_partition(void *d_ptr, size_t n, int dtype, uint64_t pivot, size_t *split)
+{
+    if (!split)
+        return fail_msg(SS_EINVAL, "split must not be NULL");
+    return ss_partition_ex(d_ptr, n, dtype, pivot, nullptr, nullptr, nullptr, split, nullptr);
+}
+
+size_t ss_aux_bytes(size_t n, int dtype, int algo)
+{
+    if (!elem_size(dtype))
+        return 0;
+    const size_t ws = ((size_t)kMaxLevels * 2 * kMaxGrid + (size_t)kMaxLevels * kCtlWords + kResultWords) *
+                      sizeof(uint64_t);
+    if (algo == SS_LOWSPACE)
+        return ws + lowspace_aux_bytes(n);
+    return ws;
+}
+
+const char *ss_strerror(int code)
+{
+    switch (code) {
+    case SS_OK: return "success";
+    case SS_EINVAL: return "invalid argument";
+    case SS_ENOMEM: return "device workspace allocation failed";
+    case SS_EDEVICE: return "HIP runtime or kernel failure";
+    case SS_EUNSUPPORTED: return "unsupported combination";
+    case SS_EINCOMPLETE: return "recursion budget exhausted";
+    default: return "unknown status";
+    }
+}
+
+const char *ss_last_error(void) { return t_last_error.c_str(); }
+
+int ss_device_info(int *compute_units, int *lds_per_block, int *arch_major, int *arch_minor)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    int cus = 0, lds = 0;
+    int rc = device_info(dev, &cus, &lds);
+    if (rc)
+        return rc;
+    if (compute_units)
+        *compute_units = cus;
+    if (lds_per_block)
+        *lds_per_block = lds;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (arch_major)
+        *arch_major = g_dev[dev].major;
+    if (arch_minor)
+        *arch_minor = g_dev[dev].minor;
+    return SS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// ss_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "ss.h"
+#include "ss_common.h"
+
+namespace ss {
+
+constexpr int kMaxLevels = 32;      // level records / partial buffers kept per workspace
+constexpr int kMaxGrid = 4096;      // upper bound of workgroups in a level launch
+constexpr int kResultWords = 8;     // done, split, vmin, vmax, ...
+constexpr uint32_t kHostLevelCap = 512;
+
+struct Workspace {
+    uint64_t *part = nullptr;    // kMaxLevels x 2 x kMaxGrid partials (device)
+    uint64_t *ctl = nullptr;     // kMaxLevels x kCtlWords level records (device)
+    uint64_t *result = nullptr;  // kResultWords (device)
+    uint64_t *host = nullptr;    // pinned copy of ctl + result
+    size_t part_words = 0, ctl_words = 0;
+    size_t bytes = 0;
+    hipEvent_t ev[4] = {};
+};
+
+struct Resolved {
+    int algo;
+    int w;
+    uint32_t b, log2b;
+    uint32_t tile;
+    uint32_t s_max;
+    uint32_t levels;
+    uint64_t seed;
+    uint32_t flags;
+};
+
+struct RunOut {
+    uint64_t split;
+    bool done;
+    uint64_t vmin, vmax;
+    uint32_t grid;
+    uint32_t levels_run;
+    uint32_t launches;
+    uint64_t aux_bytes;
+    float first_level_ms, total_ms;
+    uint64_t level_lo[SS_MAX_LEVELS], level_hi[SS_MAX_LEVELS];
+    uint32_t level_g[SS_MAX_LEVELS], level_s[SS_MAX_LEVELS];
+};
+
+struct Variant {
+    int dtype;
+    uint32_t tile;
+    int nt;
+    hipError_t (*launch)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+    const void *(*fn)(bool first);
+};
+
+template <typename T, int NT, int TB>
+hipError_t launch_level(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+template <typename T, int NT, int TB>
+const void *level_fn(bool first);
+hipError_t launch_finish(const uint64_t *prev, uint32_t count, uint64_t *result, uint64_t *d_split,
+                         hipStream_t st);
+hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
+                          uint64_t *result, uint64_t *d_split, hipStream_t st);
+
+int fail_device(hipError_t e, const char *what);
+int fail_msg(int code, const std::string &msg);
+int elem_size(int dtype);
+int check_array(const void *d_ptr, size_t n, int dtype);
+int resolve_params(const ss_params *p, int dtype, Resolved *r);
+int device_info(int dev, int *cus, int *lds);
+int occupancy(int dev, const void *fn, int nt, int *blocks);
+int get_workspace(int dev, void *stream, Workspace **out);
+void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
+int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                  uint64_t *d_split, bool sync, RunOut *ro);
+
+int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                       uint64_t *d_split, size_t *h_split, ss_stats *stats);
+size_t lowspace_aux_bytes(size_t n);
+
+}  // namespace ss

@@ -1,0 +1,92 @@
+// ss_probe.hip -- memory-bandwidth probes: the GPU counterpart of the
+// paper's read bandwidth and read/write bandwidth measurements (Section 5.1,
+// "The Memory-Bandwidth Limitation"), used as the attainable roofline of an
+// in-place pass.  Mode 0 reads every 16-byte word once; mode 1 reads every
+// word and immediately overwrites it (with the same value, xor-ed with a
+// runtime zero the compiler cannot fold).
+#include "ss_device.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+constexpr int kProbeNT = 256, kProbeUnroll = 4;
+
+__global__ void __launch_bounds__(kProbeNT) k_probe_read(const v4u *p, uint64_t nvec, uint32_t *sink)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kProbeNT;
+    uint64_t i = (uint64_t)blockIdx.x * kProbeNT + threadIdx.x;
+    v4u acc = {0u, 0u, 0u, 0u};
+    for (; i + (kProbeUnroll - 1) * stride < nvec; i += kProbeUnroll * stride) {
+        v4u v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++)
+            v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++)
+            acc ^= v[u];
+    }
+    for (; i < nvec; i += stride)
+        acc ^= p[i];
+    const uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+    if (x == 0x9E3779B9u)  // practically never; keeps the loads alive
+        sink[blockIdx.x] = x;
+}
+
+__global__ void __launch_bounds__(kProbeNT) k_probe_rw(v4u *p, uint64_t nvec, uint32_t zero)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kProbeNT;
+    uint64_t i = (uint64_t)blockIdx.x * kProbeNT + threadIdx.x;
+    for (; i + (kProbeUnroll - 1) * stride < nvec; i += kProbeUnroll * stride) {
+        v4u v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++)
+            v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++)
+            p[i + u * stride] = v[u] ^ zero;
+    }
+    for (; i < nvec; i += stride)
+        p[i] = p[i] ^ zero;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" int ss_probe_bandwidth(void *d_ptr, size_t bytes, int mode, void *stream, float *ms)
+{
+    if (!d_ptr || bytes == 0 || bytes % 16 || ((uintptr_t)d_ptr % 16) || (mode != 0 && mode != 1) || !ms)
+        return fail_msg(SS_EINVAL, "probe: need a 16-byte aligned buffer, bytes % 16 == 0, mode 0/1, ms");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    int cus = 0, lds = 0;
+    int rc = device_info(dev, &cus, &lds);
+    if (rc)
+        return rc;
+    Workspace *ws = nullptr;
+    rc = get_workspace(dev, stream, &ws);
+    if (rc)
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t nvec = bytes / 16;
+    uint64_t want = (nvec + (uint64_t)kProbeNT * kProbeUnroll - 1) / ((uint64_t)kProbeNT * kProbeUnroll);
+    const uint32_t grid = (uint32_t)(want < (uint64_t)cus * 16 ? (want ? want : 1) : (uint64_t)cus * 16);
+    if ((e = hipEventRecord(ws->ev[2], st)) != hipSuccess)
+        return fail_device(e, "hipEventRecord");
+    if (mode == 0)
+        hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(kProbeNT), 0, st, (const v4u *)d_ptr, nvec,
+                           (uint32_t *)ws->result);
+    else
+        hipLaunchKernelGGL(k_probe_rw, dim3(grid), dim3(kProbeNT), 0, st, (v4u *)d_ptr, nvec, 0u);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return fail_device(e, "probe launch");
+    if ((e = hipEventRecord(ws->ev[3], st)) != hipSuccess)
+        return fail_device(e, "hipEventRecord");
+    if ((e = hipEventSynchronize(ws->ev[3])) != hipSuccess)
+        return fail_device(e, "hipEventSynchronize");
+    if ((e = hipEventElapsedTime(ms, ws->ev[2], ws->ev[3])) != hipSuccess)
+        return fail_device(e, "hipEventElapsedTime");
+    return SS_OK;
+}

@@ -1,0 +1,254 @@
+"""GPU parity of the Smoothed Striding / Strided partition against the CPU oracle.
+
+Every case generates its input on the host from the shared seeded generator,
+copies it to the device, runs the library through its C ABI, and compares
+with the oracle run on the same input: the split index exactly and the sorted
+contents of both sides exactly (the arrangement inside a side is not unique).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = (1 << 64) - 1
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(a: np.ndarray):
+    torch = _torch()
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32).copy()).cuda()
+    return torch.from_numpy(a.view(np.int64).copy()).cuda()
+
+
+def to_host(t, like: np.ndarray) -> np.ndarray:
+    h = t.cpu().numpy()
+    return h.view(like.dtype).reshape(like.shape)
+
+
+def gen(kind: str, n: int, seed: int) -> np.ndarray:
+    if kind == "u32":
+        return workloads.keys_u32(n, seed)
+    if kind == "u64":
+        return workloads.keys_u64(n, seed)
+    return workloads.records_kv(n, seed)
+
+
+def check_against_oracle(ss, a0: np.ndarray, pivot: int, **kw):
+    t = to_device(a0)
+    split = ss.partition(t, pivot, **kw)
+    out = to_host(t, a0)
+    ref = a0.copy()
+    rsplit = oracle.partition(ref, pivot)
+    assert split == rsplit, (split, rsplit)
+    gl, gr = oracle.sorted_sides(out, split)
+    rl, rr = oracle.sorted_sides(ref, rsplit)
+    assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+    assert oracle.is_partitioned(out, pivot, split)
+    return out, split
+
+
+def test_config1_median_u64(ss):
+    # 2^20 uint64 keys, exact median pivot, 128-byte lines (b = 16)
+    a0 = workloads.keys_u64(1 << 20, workloads.config_seed(0))
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    out, split = check_against_oracle(ss, a0, p, b=16)
+    assert split == 1 << 19
+
+
+SIZES = [1, 2, 3, 15, 16, 17, 31, 127, 128, 129, 1000, 8191, 8192, 8193, 16385, 65535, 65537, 100003, 300001]
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_shapes_and_pivots(ss, kind):
+    for n in SIZES:
+        a0 = gen(kind, n, 1000 + n)
+        keys = a0[:, 0] if a0.ndim == 2 else a0
+        kmin, kmax = int(keys.min()), int(keys.max())
+        pivots = {0, kmin, kmin + 1, kmax, kmax + 1, U64MAX, workloads.pivot_at_quantile_np(a0, 0.5),
+                  workloads.pivot_at_quantile_np(a0, 0.01)}
+        if kind == "u32":
+            pivots |= {1 << 32, (1 << 32) - 1}
+        for p in sorted(pivots):
+            check_against_oracle(ss, a0, p)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_duplicates_and_structured_inputs(ss, kind):
+    n = 70001
+    base = gen(kind, n, 5)
+    keys = base[:, 0] if base.ndim == 2 else base
+    variants = {
+        "few": keys % 7,
+        "equal": np.zeros_like(keys) + 3,
+        "ascending": np.sort(keys),
+        "descending": np.sort(keys)[::-1].copy(),
+    }
+    for name, k in variants.items():
+        a0 = base.copy()
+        if a0.ndim == 2:
+            a0[:, 0] = k
+        else:
+            a0[:] = k
+        for q in (0.0, 0.3, 0.5, 0.99):
+            check_against_oracle(ss, a0, workloads.pivot_at_quantile_np(a0, q))
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_unaligned_subarrays(ss, kind):
+    # Sub-tensors starting at every element offset inside a 128-byte line.
+    torch = _torch()
+    n = 50000
+    full = gen(kind, n + 64, 77)
+    t_full = to_device(full)
+    step = {"u32": 1, "u64": 1, "kv": 1}[kind]
+    for off in range(0, 33, step):
+        if off + 1000 > n:
+            break
+        length = n - off - (off * 37) % 500
+        sub_host = full[off:off + length].copy()
+        p = workloads.pivot_at_quantile_np(sub_host, 0.4)
+        t = t_full.clone()
+        view = t[off:off + length]
+        assert view.is_contiguous()
+        split = ss.partition(view, p)
+        out = to_host(t, full)
+        # outside the sub-array nothing changed
+        assert np.array_equal(out[:off], full[:off]) and np.array_equal(out[off + length:], full[off + length:])
+        ref = sub_host.copy()
+        assert split == oracle.partition(ref, p)
+        gl, gr = oracle.sorted_sides(out[off:off + length], split)
+        rl, rr = oracle.sorted_sides(ref, split)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+
+
+def _group_of_position(n, b, g, s, X):
+    line = np.arange((n + b - 1) // b)
+    j = line // g
+    r = line % g
+    grp = (r - X[j].astype(np.int64)) % g
+    return np.repeat(grp, b)[:n]
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+@pytest.mark.parametrize("algo", ["smoothed", "strided"])
+def test_one_level_matches_oracle_level(ss, kind, algo):
+    """One Partial Partition Step: (v_min, v_max), the side of every position and
+    the multiset of every group equal the oracle's step with the same offsets."""
+    for n, seed, q in ((1 << 18, 1, 0.5), (123457, 2, 0.1), (300000, 3, 0.9), (40000, 4, 0.5)):
+        a0 = gen(kind, n, seed)
+        p = workloads.pivot_at_quantile_np(a0, q)
+        t = to_device(a0)
+        split, st = ss.partition(t, p, stats=True, one_level=True, algo=algo, seed=1234 + seed)
+        out = to_host(t, a0)
+        g, s, b = st["level_g"][0], st["level_s"][0], st["b"]
+        assert st["level_lo"][0] == 0 and st["level_hi"][0] == n
+        assert g >= 2
+        assert s * g * b >= n > (s - 1) * g * b
+        X = np.zeros(s, np.uint32) if algo == "strided" else oracle.ss_offsets(1234 + seed, 0, g, s)
+        ref = a0.copy()
+        vmin, vmax, c, v = oracle.ss_partial_step(ref, b, g, s, X, p)
+        assert (st["vmin"], st["vmax"]) == (vmin, vmax)
+        gk = out[:, 0] if out.ndim == 2 else out
+        rk = ref[:, 0] if ref.ndim == 2 else ref
+        assert np.array_equal(gk < p, rk < p)
+        grp = _group_of_position(n, b, g, s, X)
+        order_g = np.lexsort((gk, grp))
+        order_r = np.lexsort((rk, grp))
+        assert np.array_equal(gk[order_g], rk[order_r])
+
+
+def test_same_seed_same_bytes_and_other_seeds_correct(ss):
+    a0 = workloads.keys_u64(500000, 9)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    t1, t2 = to_device(a0), to_device(a0)
+    s1 = ss.partition(t1, p, seed=42)
+    s2 = ss.partition(t2, p, seed=42)
+    assert s1 == s2
+    assert bool((t1 == t2).all())
+    for sd in (1, 2, 3):
+        check_against_oracle(ss, a0, p, seed=sd)
+
+
+@pytest.mark.parametrize("tile", [32768, 65536])
+@pytest.mark.parametrize("line_bytes", [64, 128, 256, 512, 1024, 4096])
+def test_tiles_and_line_sizes(ss, tile, line_bytes):
+    for kind, w in (("u32", 4), ("u64", 8), ("kv", 16)):
+        if line_bytes > tile:
+            continue
+        a0 = gen(kind, 200003, line_bytes + w)
+        p = workloads.pivot_at_quantile_np(a0, 0.37)
+        check_against_oracle(ss, a0, p, b=line_bytes // w, tile_bytes=tile)
+
+
+def test_small_level_budget_continues_from_host(ss):
+    a0 = workloads.keys_u64(1 << 20, 3)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    _, split = check_against_oracle(ss, a0, p, max_levels=1)
+    t = to_device(a0)
+    split2, st = ss.partition(t, p, stats=True, max_levels=1)
+    assert split2 == split and st["levels"] >= 2
+
+
+def test_async_split_and_empty(ss):
+    torch = _torch()
+    a0 = workloads.keys_u64(1 << 18, 4)
+    p = workloads.pivot_at_quantile_np(a0, 0.25)
+    t = to_device(a0)
+    d = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+    ss.partition_async(t, p, d)
+    torch.cuda.synchronize()
+    assert int(d.item()) == oracle.count_less(a0, p)
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    assert ss.partition(e, 5) == 0
+    assert ss.partition_plain(to_device(a0), p) == oracle.count_less(a0, p)
+
+
+def test_stats_levels_and_bytes(ss):
+    a0 = workloads.keys_u64(1 << 22, 6)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    t = to_device(a0)
+    split, st = ss.partition(t, p, stats=True, time=True)
+    assert split == 1 << 21
+    assert st["levels"] >= 2 and st["level_lo"][0] == 0 and st["level_hi"][0] == 1 << 22
+    for k in range(1, st["levels"]):  # each level works inside the previous one's middle
+        assert st["level_lo"][k - 1] <= st["level_lo"][k] < st["level_hi"][k] <= st["level_hi"][k - 1]
+    assert st["bytes_moved"] >= 2 * 8 * (1 << 22)
+    assert st["first_level_ms"] > 0 and st["total_ms"] >= st["first_level_ms"]
+    assert st["aux_bytes"] == ss.aux_bytes(1 << 22, ss.SS_U64)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_strided_parity(ss, kind):
+    for n, q in ((1 << 20, 0.5), (99991, 0.2), (5000, 0.7), (1, 0.5)):
+        a0 = gen(kind, n, 31 + n)
+        check_against_oracle(ss, a0, workloads.pivot_at_quantile_np(a0, q), algo="strided")
+
+
+@pytest.mark.slow
+def test_full_size_2p30_properties(ss):
+    """2^30 uint64 keys (the benchmark shape): split equals the oracle's count on the
+    host copy, every element is on its side, and the multiset is unchanged."""
+    torch = _torch()
+    n = 1 << 30
+    t = workloads.keys_u64_torch(n, workloads.config_seed(1), "cuda")
+    p = workloads.pivot_at_quantile_torch(t, 0.5)
+    host_in = t.cpu().numpy().view(np.uint64)
+    count = oracle.count_less(host_in, p)
+    fp_in = oracle.fingerprint(host_in)
+    del host_in
+    split, st = ss.partition(t, p, stats=True)
+    assert split == count == n // 2
+    host_out = t.cpu().numpy().view(np.uint64)
+    assert oracle.is_partitioned(host_out, p, split)
+    assert oracle.fingerprint(host_out) == fp_in
+    assert st["levels"] >= 2
+    del t
+    torch.cuda.empty_cache()
