@@ -36,7 +36,7 @@ WORKLOADS = {
     "partition_u64_2p30_q0.01": ("u64", 30, 0.01),
     "partition_u64_2p30_desc": ("u64", 30, "desc"),
 }
-LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level.hip", "paper_2004_12532_amd/csrc/ss_device.h",
+LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_device.h",
                  "paper_2004_12532_amd/csrc/ss_common.h"]
 COUNTER_FILE = os.path.join(ROOT, "profiles", "level0_u64_2p30_counters.json")
 
@@ -204,7 +204,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel": "k_level<uint64_t,256,65536,first> (first Partial Partition Step)",
+            "kernel": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "probe": probe,

@@ -84,20 +84,36 @@ enum ss_status {
                                   successors, reported in ss_stats (Section 4).  For tests. */
 #define SS_FLAG_TIME 2u        /* time the first-level kernel and the whole call with HIP events on
                                   the call's stream; reported in ss_stats (synchronizes). */
+#define SS_FLAG_STREAM 4u      /* register engines: non-temporal (streaming) loads and stores */
+#define SS_FLAG_XCD_ORDER 8u   /* register engines: consecutive groups on the same XCD */
 
 /* Tuning parameters; a zero field means "choose automatically". */
 typedef struct ss_params {
     int32_t algo;         /* ss_algo */
     uint32_t b;           /* elements per cache line (the paper's b); b * sizeof(element) must be a
-                             power of two between 64 and 4096 bytes.  Default: 128-byte lines. */
-    uint32_t tile_bytes;  /* bytes of one group's tile in LDS: 32768 or 65536; the group size is
-                             s <= tile_bytes / (b * sizeof(element)) lines.  Default 65536. */
+                             power of two between 64 and 4096 bytes.  Default: 512-byte lines. */
+    uint32_t tile_bytes;  /* bytes of one group (s * b * sizeof(element) at most): 32768, 65536 or
+                             131072 (the last only with SS_ENGINE_REGS).  Default: chosen per engine. */
     uint32_t max_levels;  /* recursion levels launched before the host looks at the result (1..32).
-                             Default 10. */
+                             Default 8. */
     uint64_t seed;        /* seed of the random chunk offsets X_j; 0 selects a fixed default */
     uint32_t flags;       /* SS_FLAG_* */
-    uint32_t reserved;    /* must be 0 */
+    uint32_t engine;      /* workgroup body of a Partial Partition Step: SS_ENGINE_* (0 = auto) */
 } ss_params;
+
+/* Workgroup bodies of the Partial Partition Step.  Both compute the same
+ * stable partition of every group, so results are identical.
+ * SS_ENGINE_LDS  : the group is permuted through an LDS tile and written back
+ *                  as whole lines.
+ * SS_ENGINE_REGS : the group stays in registers and every element is stored
+ *                  straight to its destination (no LDS tile, higher occupancy).
+ * SS_ENGINE_REGS2: as SS_ENGINE_REGS with two register buffers: the next
+ *                  group's loads are in flight while the current one is
+ *                  partitioned (32768- or 65536-byte groups). */
+#define SS_ENGINE_AUTO 0u
+#define SS_ENGINE_LDS 1u
+#define SS_ENGINE_REGS 2u
+#define SS_ENGINE_REGS2 3u
 
 #define SS_MAX_LEVELS 32
 

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(_SO)
 SS_U32, SS_U64, SS_KV16 = 1, 2, 3
 SMOOTHED, STRIDED, LOWSPACE = 0, 1, 2
 ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE}
-FLAG_ONE_LEVEL, FLAG_TIME = 1, 2
+FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER = 1, 2, 4, 8
 MAX_LEVELS = 32
 STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",
           -5: "SS_EINCOMPLETE"}
@@ -38,7 +38,7 @@ STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "S
 class Params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("b", ctypes.c_uint32), ("tile_bytes", ctypes.c_uint32),
                 ("max_levels", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("engine", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -127,10 +127,16 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False) -> Params:
+ENGINES = {"auto": 0, "lds": 1, "regs": 2, "regs2": 3}
+
+
+def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False,
+                engine="auto", stream=False, xcd_order=False) -> Params:
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
-    flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0)
-    return Params(a, b, tile_bytes, max_levels, seed, flags, 0)
+    flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0) | (FLAG_STREAM if stream else 0) \
+        | (FLAG_XCD_ORDER if xcd_order else 0)
+    e = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    return Params(a, b, tile_bytes, max_levels, seed, flags, e)
 
 
 def partition(t, pivot: int, *, stats: bool = False, stream=None, **kw):

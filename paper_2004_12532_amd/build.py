@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ss_level.hip", "ss_strided.hip", "ss_lowspace.hip", "ss_quicksort.hip", "ss_batched.hip",
+SOURCES = ["ss_level.hip", "ss_level_rs.hip", "ss_strided.hip", "ss_lowspace.hip", "ss_quicksort.hip", "ss_batched.hip",
            "ss_probe.hip", "ss_api.cpp"]
 
 FLAGS = [

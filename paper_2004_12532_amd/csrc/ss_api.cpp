@@ -110,12 +110,16 @@ int get_workspace(int dev, void *stream, Workspace **out)
     }
     w.ctl = w.part + w.part_words;
     w.result = w.ctl + w.ctl_words;
-    e = hipHostMalloc((void **)&w.host, (w.ctl_words + kResultWords) * sizeof(uint64_t), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&w.host, (w.ctl_words + kResultWords) * sizeof(uint64_t),
+                      hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) {
         (void)hipFree(w.part);
         (void)hipGetLastError();
         return fail_msg(SS_ENOMEM, std::string("workspace hipHostMalloc: ") + hipGetErrorString(e));
     }
+    e = hipHostGetDevicePointer((void **)&w.host_dev, w.host, 0);
+    if (e != hipSuccess)
+        return fail_device(e, "hipHostGetDevicePointer");
     for (int k = 0; k < 4; k++) {
         e = hipEventCreate(&w.ev[k]);
         if (e != hipSuccess)
@@ -157,19 +161,28 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r)
         q = *p;
     if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE)
         return fail_msg(SS_EINVAL, "unknown algo");
-    if (q.reserved != 0 || (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME)))
-        return fail_msg(SS_EINVAL, "unknown flags or nonzero reserved field");
-    const uint32_t tile = q.tile_bytes ? q.tile_bytes : 65536u;
-    if (tile != 32768u && tile != 65536u)
-        return fail_msg(SS_EINVAL, "tile_bytes must be 32768 or 65536");
-    const uint32_t b = q.b ? q.b : 128u / w;
+    if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER))
+        return fail_msg(SS_EINVAL, "unknown flags");
+    if (q.engine > SS_ENGINE_REGS2)
+        return fail_msg(SS_EINVAL, "unknown engine");
+    const uint32_t engine = q.engine ? q.engine : kDefaultEngine;
+    const uint32_t tile = q.tile_bytes ? q.tile_bytes
+                         : engine == SS_ENGINE_LDS  ? 32768u
+                         : engine == SS_ENGINE_REGS2 ? 65536u
+                                                     : kDefaultRegsTile;
+    if (tile != 32768u && tile != 65536u && !(tile == 131072u && engine == SS_ENGINE_REGS))
+        return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (single-buffer register engine) 131072");
+    if ((q.flags & SS_FLAG_STREAM) && engine == SS_ENGINE_LDS)
+        return fail_msg(SS_EINVAL, "streaming hints apply to the register engines");
+    const uint32_t b = q.b ? q.b : kDefaultLineBytes / w;
     const uint64_t line = (uint64_t)b * w;
     if (b == 0 || (b & (b - 1)) || line < 64 || line > 4096 || line > tile)
         return fail_msg(SS_EINVAL, "b * sizeof(element) must be a power of two in [64, 4096] bytes");
-    const uint32_t levels = q.max_levels ? q.max_levels : 10u;
+    const uint32_t levels = q.max_levels ? q.max_levels : kDefaultLevels;
     if (levels > (uint32_t)kMaxLevels)
         return fail_msg(SS_EINVAL, "max_levels above 32");
     r->algo = q.algo;
+    r->engine = engine;
     r->w = w;
     r->b = b;
     r->log2b = ilog2(b);
@@ -181,18 +194,27 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r)
     return SS_OK;
 }
 
-const Variant *pick_variant(int dtype, uint32_t tile)
+#define SS_LDS_VARIANT(D, T, NT, TB) {D, SS_ENGINE_LDS, TB, false, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>}
+#define SS_RS_VARIANT(D, T, E, NT, NV, NTMP, DB) \
+    {D, E, NT * NV * 16, NTMP, NT, &launch_level_rs<T, NT, NV, NTMP, DB>, &level_rs_fn<T, NT, NV, NTMP, DB>}
+#define SS_RS_ALL(E, NT, NV, NTMP, DB)                                                     \
+    SS_RS_VARIANT(SS_U32, uint32_t, E, NT, NV, NTMP, DB), SS_RS_VARIANT(SS_U64, uint64_t, E, NT, NV, NTMP, DB), \
+        SS_RS_VARIANT(SS_KV16, KV, E, NT, NV, NTMP, DB)
+
+const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile, bool stream)
 {
     static const Variant v[] = {
-        {SS_U32, 65536, 256, &launch_level<uint32_t, 256, 65536>, &level_fn<uint32_t, 256, 65536>},
-        {SS_U64, 65536, 256, &launch_level<uint64_t, 256, 65536>, &level_fn<uint64_t, 256, 65536>},
-        {SS_KV16, 65536, 256, &launch_level<KV, 256, 65536>, &level_fn<KV, 256, 65536>},
-        {SS_U32, 32768, 256, &launch_level<uint32_t, 256, 32768>, &level_fn<uint32_t, 256, 32768>},
-        {SS_U64, 32768, 256, &launch_level<uint64_t, 256, 32768>, &level_fn<uint64_t, 256, 32768>},
-        {SS_KV16, 32768, 256, &launch_level<KV, 256, 32768>, &level_fn<KV, 256, 32768>},
+        SS_LDS_VARIANT(SS_U32, uint32_t, 256, 65536), SS_LDS_VARIANT(SS_U64, uint64_t, 256, 65536),
+        SS_LDS_VARIANT(SS_KV16, KV, 256, 65536),      SS_LDS_VARIANT(SS_U32, uint32_t, 256, 32768),
+        SS_LDS_VARIANT(SS_U64, uint64_t, 256, 32768), SS_LDS_VARIANT(SS_KV16, KV, 256, 32768),
+        SS_RS_ALL(SS_ENGINE_REGS, 256, 8, false, false),  SS_RS_ALL(SS_ENGINE_REGS, 512, 8, false, false),
+        SS_RS_ALL(SS_ENGINE_REGS, 512, 16, false, false), SS_RS_ALL(SS_ENGINE_REGS, 256, 8, true, false),
+        SS_RS_ALL(SS_ENGINE_REGS, 512, 8, true, false),   SS_RS_ALL(SS_ENGINE_REGS, 512, 16, true, false),
+        SS_RS_ALL(SS_ENGINE_REGS2, 512, 4, false, true),  SS_RS_ALL(SS_ENGINE_REGS2, 512, 8, false, true),
+        SS_RS_ALL(SS_ENGINE_REGS2, 512, 4, true, true),   SS_RS_ALL(SS_ENGINE_REGS2, 512, 8, true, true),
     };
     for (const Variant &x : v)
-        if (x.dtype == dtype && x.tile == tile)
+        if (x.dtype == dtype && x.engine == engine && x.tile == tile && x.stream == stream)
             return &x;
     return nullptr;
 }
@@ -231,7 +253,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     rc = get_workspace(dev, st, &ws);
     if (rc)
         return rc;
-    const Variant *V = pick_variant(dtype, R.tile);
+    const Variant *V = pick_variant(dtype, R.engine, R.tile, (R.flags & SS_FLAG_STREAM) != 0);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
     int occ = 0;
@@ -242,6 +264,21 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     if (P > (uint32_t)kMaxGrid)
         P = kMaxGrid;
     ro->grid = P;
+    // Levels from the third on work on regions a few hundred times smaller
+    // than the array; there a group is latency-bound, so they use 32 KiB
+    // groups of 128-byte lines (more, shorter groups per level).
+    const Variant *Vt = pick_variant(dtype, R.engine == SS_ENGINE_LDS ? SS_ENGINE_LDS : SS_ENGINE_REGS, 32768u,
+                                     R.engine != SS_ENGINE_LDS && (R.flags & SS_FLAG_STREAM) != 0);
+    if (!Vt)
+        return fail_msg(SS_EUNSUPPORTED, "no tail kernel variant");
+    int occ_t = 0;
+    rc = occupancy(dev, Vt->fn(false), Vt->nt, &occ_t);
+    if (rc)
+        return rc;
+    uint32_t Pt = (uint32_t)(occ_t * cus);
+    if (Pt > (uint32_t)kMaxGrid)
+        Pt = kMaxGrid;
+    const uint32_t log2b_t = (uint32_t)ilog2(128 / R.w), s_max_t = 32768u / 128u;
     ro->aux_bytes = ws->bytes;
     ro->launches = 0;
 
@@ -262,27 +299,36 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         a.log2b = R.log2b;
         a.s_max = R.s_max;
         a.strided = strided ? 1u : 0u;
+        a.order = (R.flags & SS_FLAG_XCD_ORDER) ? 1u : 0u;
         uint32_t prev_count = 0;
         const uint64_t *prev = nullptr;
+        const uint64_t *prev_ctl = nullptr;
+        const uint32_t first_level = level;
+        // Level k of this round keeps its partials and record in slot k.
         for (uint32_t k = 0; k < budget; k++, level++) {
             const bool first = k == 0;
-            uint32_t grid = P;
+            const bool tail = level >= 2;
+            const Variant *Vl = tail ? Vt : V;
+            a.log2b = tail ? log2b_t : R.log2b;
+            a.s_max = tail ? s_max_t : R.s_max;
+            uint32_t grid = tail ? Pt : P;
             if (first) {
-                const Geo G = plan_geo((uintptr_t)base, lo, hi, R.w, R.log2b, R.s_max);
-                grid = G.g < P ? G.g : P;
+                const Geo G = plan_geo((uintptr_t)base, lo, hi, R.w, a.log2b, a.s_max);
+                grid = G.g < grid ? G.g : grid;
                 a.lo = lo;
                 a.hi = hi;
             }
             a.level = level;
             a.prev = prev;
+            a.prev_ctl = prev_ctl;
             a.prev_count = prev_count;
-            a.out = ws->part + (size_t)(level % kMaxLevels) * 2 * kMaxGrid;
-            a.ctl = ws->ctl + (size_t)(level % kMaxLevels) * kCtlWords;
+            a.out = ws->part + (size_t)k * 2 * kMaxGrid;
+            a.ctl = ws->ctl + (size_t)k * kCtlWords;
             if (timing && level == 0) {
                 if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
                     return fail_device(e, "hipEventRecord");
             }
-            if ((e = V->launch(first, grid, a, st)) != hipSuccess)
+            if ((e = Vl->launch(first, grid, a, st)) != hipSuccess)
                 return fail_device(e, "level kernel launch");
             ro->launches++;
             if (timing && level == 0) {
@@ -290,34 +336,33 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                     return fail_device(e, "hipEventRecord");
             }
             prev = a.out;
+            prev_ctl = a.ctl;
             prev_count = grid;
         }
+        uint64_t *host = sync ? ws->host_dev : nullptr;
         if (strided && !(R.flags & SS_FLAG_ONE_LEVEL)) {
             // Serial Cleanup Step: one workgroup partitions [v_min, v_max).
-            if ((e = launch_cleanup(dtype, base, pivot, prev, prev_count, ws->result, d_split, st)) !=
+            if ((e = launch_cleanup(dtype, base, pivot, prev, prev_count, ws->result, d_split, ws->ctl, host, st)) !=
                 hipSuccess)
                 return fail_device(e, "cleanup kernel launch");
             ro->launches++;
         } else {
-            if ((e = launch_finish(prev, prev_count, ws->result, d_split, st)) != hipSuccess)
+            if ((e = launch_finish(prev, prev_count, prev_ctl, ws->result, d_split, ws->ctl, budget, host, st)) !=
+                hipSuccess)
                 return fail_device(e, "finish kernel launch");
             ro->launches++;
         }
         ro->levels_run = level;
         if (!sync)
             return SS_OK;
-        e = hipMemcpyAsync(ws->host, ws->ctl, (ws->ctl_words + kResultWords) * sizeof(uint64_t),
-                           hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess)
-            return fail_device(e, "hipMemcpyAsync");
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return fail_device(e, "hipStreamSynchronize");
-        const uint64_t *res = ws->host + ws->ctl_words;
-        // level records of this round
-        for (uint32_t l = level - budget; l < level; l++) {
+        const volatile uint64_t *res = ws->host;
+        for (uint32_t k = 0; k < budget; k++) {
+            const uint32_t l = first_level + k;
             if (l >= (uint32_t)SS_MAX_LEVELS)
                 break;
-            const uint64_t *c = ws->host + (size_t)(l % kMaxLevels) * kCtlWords;
+            const volatile uint64_t *c = ws->host + kResultWordsDev + (size_t)k * kCtlWords;
             ro->level_lo[l] = c[0];
             ro->level_hi[l] = c[1];
             ro->level_g[l] = (uint32_t)c[2];

@@ -75,6 +75,7 @@ struct LevelArgs {
     uint64_t pivot;
     uint64_t seed;
     const uint64_t *prev;   // previous level's partials {vmin, vmax} per workgroup (non-first levels)
+    const uint64_t *prev_ctl;  // previous level's record (its g tells whether one partial suffices)
     uint64_t *out;          // this level's partials
     uint64_t *ctl;          // this level's record, written by workgroup 0: lo, hi, g, s
     uint64_t lo, hi;        // region of a first level
@@ -83,9 +84,10 @@ struct LevelArgs {
     uint32_t log2b;         // log2 of elements per line
     uint32_t s_max;         // lines-per-group bound
     uint32_t strided;       // 1: every offset is 0 (the Strided Algorithm)
-    uint32_t pad;
+    uint32_t order;         // 1: XCD-grouped assignment of groups to workgroups
 };
 
-constexpr int kCtlWords = 8;  // words per level record
+constexpr int kCtlWords = 8;        // words per level record
+constexpr int kResultWordsDev = 8;  // result words ahead of the level records in the host copy
 
 }  // namespace ss

@@ -122,6 +122,22 @@ __device__ __forceinline__ void reduce_partials(const uint64_t *prev, uint32_t c
     hi = mx;
 }
 
+// Region of a non-first level: [v_min, v_max) of the previous level.  When
+// the previous level had at most one group (g <= 1: it finished the
+// partition, or had nothing left to do), workgroup 0's partial is the whole
+// answer and the other partials need not be read.
+template <int NT>
+__device__ __forceinline__ void prev_region(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl,
+                                            uint64_t *red, uint64_t &lo, uint64_t &hi)
+{
+    if (prev_ctl && prev_ctl[2] <= 1) {
+        lo = prev[0];
+        hi = prev[1] > prev[0] ? prev[1] : prev[0];
+        return;
+    }
+    reduce_partials<NT>(prev, count, red, lo, hi);
+}
+
 // Key of an element held as its own type.
 __device__ __forceinline__ uint64_t key_of(uint32_t x) { return x; }
 __device__ __forceinline__ uint64_t key_of(uint64_t x) { return x; }

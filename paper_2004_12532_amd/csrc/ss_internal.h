@@ -13,14 +13,19 @@ namespace ss {
 
 constexpr int kMaxLevels = 32;      // level records / partial buffers kept per workspace
 constexpr int kMaxGrid = 4096;      // upper bound of workgroups in a level launch
-constexpr int kResultWords = 8;     // done, split, vmin, vmax, ...
+constexpr int kResultWords = kResultWordsDev;  // done, split, vmin, vmax, ...
 constexpr uint32_t kHostLevelCap = 512;
+constexpr uint32_t kDefaultEngine = SS_ENGINE_REGS;
+constexpr uint32_t kDefaultRegsTile = 131072;
+constexpr uint32_t kDefaultLineBytes = 512;
+constexpr uint32_t kDefaultLevels = 8;
 
 struct Workspace {
     uint64_t *part = nullptr;    // kMaxLevels x 2 x kMaxGrid partials (device)
     uint64_t *ctl = nullptr;     // kMaxLevels x kCtlWords level records (device)
     uint64_t *result = nullptr;  // kResultWords (device)
-    uint64_t *host = nullptr;    // pinned copy of ctl + result
+    uint64_t *host = nullptr;    // mapped pinned host memory: result words then level records
+    uint64_t *host_dev = nullptr;  // the same memory as seen from the device
     size_t part_words = 0, ctl_words = 0;
     size_t bytes = 0;
     hipEvent_t ev[4] = {};
@@ -28,6 +33,7 @@ struct Workspace {
 
 struct Resolved {
     int algo;
+    uint32_t engine;
     int w;
     uint32_t b, log2b;
     uint32_t tile;
@@ -52,7 +58,9 @@ struct RunOut {
 
 struct Variant {
     int dtype;
+    uint32_t engine;
     uint32_t tile;
+    bool stream;
     int nt;
     hipError_t (*launch)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
     const void *(*fn)(bool first);
@@ -62,10 +70,15 @@ template <typename T, int NT, int TB>
 hipError_t launch_level(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int TB>
 const void *level_fn(bool first);
-hipError_t launch_finish(const uint64_t *prev, uint32_t count, uint64_t *result, uint64_t *d_split,
-                         hipStream_t st);
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+const void *level_rs_fn(bool first);
+const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile, bool stream);
+hipError_t launch_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl, uint64_t *result,
+                         uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host, hipStream_t st);
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
-                          uint64_t *result, uint64_t *d_split, hipStream_t st);
+                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint64_t *host, hipStream_t st);
 
 int fail_device(hipError_t e, const char *what);
 int fail_msg(int code, const std::string &msg);

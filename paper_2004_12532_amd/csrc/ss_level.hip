@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(NT) k_level(const LevelArgs a)
         lo = a.lo;
         hi = a.hi;
     } else {
-        reduce_partials<NT>(a.prev, a.prev_count, red, lo, hi);
+        prev_region<NT>(a.prev, a.prev_count, a.prev_ctl, red, lo, hi);
     }
     if (!(lo < hi)) {
         // Previous level left no middle: the partition is complete, split = lo.
@@ -241,21 +241,31 @@ __global__ void __launch_bounds__(NT) k_level(const LevelArgs a)
 
 // Reduce the last level's partials: result[0] = 1 if the partition is
 // complete, result[1] = split (when complete), result[2..3] = (vmin, vmax).
-// d_split (nullable) receives the split or UINT64_MAX.
-__global__ void __launch_bounds__(256) k_finish(const uint64_t *prev, uint32_t count, uint64_t *result,
-                                                uint64_t *d_split)
+// d_split (nullable) receives the split or UINT64_MAX.  host (nullable, in
+// mapped host memory) receives the result words and then `nctl` level
+// records starting at `ctl`, so the host reads them without a copy.
+__global__ void __launch_bounds__(256) k_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl,
+                                                uint64_t *result, uint64_t *d_split, const uint64_t *ctl,
+                                                uint32_t nctl, uint64_t *host)
 {
     __shared__ uint64_t red[8];
     uint64_t lo, hi;
-    reduce_partials<256>(prev, count, red, lo, hi);
+    prev_region<256>(prev, count, prev_ctl, red, lo, hi);
+    const bool done = !(lo < hi);
     if (threadIdx.x == 0) {
-        const bool done = !(lo < hi);
         result[0] = done;
         result[1] = done ? lo : ~0ull;
         result[2] = lo;
         result[3] = hi;
         if (d_split)
             *d_split = done ? lo : ~0ull;
+    }
+    if (host) {
+        if (threadIdx.x < 4)
+            host[threadIdx.x] = threadIdx.x == 0 ? (uint64_t)done : threadIdx.x == 1 ? (done ? lo : ~0ull)
+                                                                   : threadIdx.x == 2 ? lo : hi;
+        for (uint32_t k = threadIdx.x; k < nctl * kCtlWords; k += 256)
+            host[kResultWordsDev + k] = ctl[k];
     }
 }
 
@@ -278,10 +288,10 @@ const void *level_fn(bool first)
                  : reinterpret_cast<const void *>(&k_level<T, NT, TB, false>);
 }
 
-hipError_t launch_finish(const uint64_t *prev, uint32_t count, uint64_t *result, uint64_t *d_split,
-                         hipStream_t st)
+hipError_t launch_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl, uint64_t *result,
+                         uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, prev, count, result, d_split);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, prev, count, prev_ctl, result, d_split, ctl, nctl, host);
     return hipGetLastError();
 }
 

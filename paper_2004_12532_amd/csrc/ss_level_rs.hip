@@ -1,0 +1,393 @@
+// ss_level_rs.hip -- register-resident Partial Partition Step.
+//
+// Same step and same result as the LDS-tile kernel (one Partial Partition
+// Step of Smoothed Striding, Section 4; stable partition of every group
+// U_i's slot sequence, so the arrangement is identical), but the group's
+// elements stay in VGPRs and each element is stored directly to its
+// destination line: predecessors to slot rank, successors to slot
+// c_i + (slot - rank).  Without an LDS tile the number of resident
+// workgroups per CU is bounded only by registers, so more of a group's bytes
+// are in flight per CU, and groups can be larger (a smaller middle region)
+// at the same occupancy.  Stores are 4/8/16-byte scattered writes; a
+// wavefront's predecessors (and successors) go to consecutive slots, so each
+// store instruction covers a few contiguous runs of lines, which the L2
+// merges into whole-line writes.
+//
+// Per group: (1) load the group's lines into registers (16-byte vectors, 8
+// lanes per 128-byte line); (2) evaluate key < pivot and count predecessors
+// per (round, wave) with ballots; (3) one wave scans those counts; (4) each
+// element's rank is recomputed from the ballots and the element is stored;
+// (5) the next group's loads are issued; (6) thread 0 folds v_i into the
+// workgroup's (v_min, v_max).
+//
+// A group whose lines are all real and that fills the whole tile (every
+// group of a level except at most the two touching the region's ends, and
+// the last partial round of small regions) takes a branch-free path; the
+// others take a general path that masks virtual elements (front padding up
+// to the line boundary, padding after the region's end).
+#include "ss_common.h"
+#include "ss_device.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+template <bool NTMP>
+__device__ __forceinline__ v4u load_vec(const char *p)
+{
+    if (NTMP)
+        return __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+    return *reinterpret_cast<const v4u *>(p);
+}
+
+template <bool NTMP, typename T>
+__device__ __forceinline__ void store_elem(const v4u &v, int e, char *p)
+{
+    if (NTMP) {
+        if constexpr (sizeof(T) == 4) {
+            __builtin_nontemporal_store(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w, reinterpret_cast<uint32_t *>(p));
+        } else if constexpr (sizeof(T) == 8) {
+            typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+            const v2u x = e == 0 ? v2u{v.x, v.y} : v2u{v.z, v.w};
+            __builtin_nontemporal_store(x, reinterpret_cast<v2u *>(p));
+        } else {
+            __builtin_nontemporal_store(v, reinterpret_cast<v4u *>(p));
+        }
+    } else {
+        Elem<T>::store1(v, e, p);
+    }
+}
+
+template <typename T, int NT, int NV, bool NTMP = false>
+struct LevelCtx {
+    static constexpr int W = sizeof(T);
+    static constexpr int LOG2W = W == 4 ? 2 : W == 8 ? 3 : 4;
+    static constexpr int V = Elem<T>::V;
+    static constexpr int NW = NT / 64;
+    static constexpr int NVEC = NT * NV;
+    static constexpr int E = NV * NW;  // (round, wave) counts
+
+    char *A0;           // line-aligned anchor of the region
+    const uint32_t *xoff;
+    uint32_t *cnt;      // E + 1 words of LDS
+    uint64_t pivot;
+    uint64_t real_end;  // virtual index past the last real element
+    uint32_t fp;        // virtual predecessors in front
+    uint32_t g, s;
+    uint32_t log2b, vpl_log2, nvec;
+    int tid, lane, wid;
+
+    __device__ __forceinline__ uint32_t line_of(uint32_t j, uint32_t i) const
+    {
+        uint32_t r = xoff[j] + i;
+        r = r >= g ? r - g : r;
+        return j * g + r;
+    }
+    __device__ __forceinline__ uint64_t vec_start(uint32_t q, uint32_t i) const
+    {
+        return ((uint64_t)line_of(q >> vpl_log2, i) << log2b) + (q & ((1u << vpl_log2) - 1)) * V;
+    }
+    __device__ __forceinline__ char *elem_ptr(uint64_t vpos) const { return A0 + (vpos << LOG2W); }
+
+    // Every slot of group i is a real element and the group fills the tile.
+    __device__ __forceinline__ bool fast(uint32_t i) const
+    {
+        if (nvec != (uint32_t)NVEC)
+            return false;
+        if (fp && line_of(0, i) == 0)
+            return false;
+        return ((uint64_t)(line_of(s - 1, i) + 1) << log2b) <= real_end;
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i) const
+    {
+#pragma unroll
+        for (int r = 0; r < NV; r++) {
+            const uint32_t q = r * NT + tid;
+            if (FAST) {
+                buf[r] = load_vec<NTMP>(elem_ptr(vec_start(q, i)));
+            } else {
+                buf[r] = v4u{0u, 0u, 0u, 0u};
+                if (q < nvec) {
+                    const uint64_t e0 = vec_start(q, i);
+                    if (e0 >= fp && e0 + V <= real_end) {
+                        buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(e0));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < V; e++)
+                            if (e0 + e >= fp && e0 + e < real_end)
+                                Elem<T>::load1(buf[r], e, elem_ptr(e0 + e));
+                    }
+                }
+            }
+        }
+    }
+
+    // Decider bits of vector r; virtual front elements count as predecessors.
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t bits_of(const v4u &v, int r, uint32_t i) const
+    {
+        uint32_t bits = 0;
+        if (FAST) {
+#pragma unroll
+            for (int e = 0; e < V; e++)
+                bits |= (uint32_t)(Elem<T>::key(v, e) < pivot) << e;
+        } else {
+            const uint32_t q = r * NT + tid;
+            if (q < nvec) {
+                const uint64_t e0 = vec_start(q, i);
+#pragma unroll
+                for (int e = 0; e < V; e++) {
+                    const uint64_t vp = e0 + e;
+                    const bool real = vp >= fp && vp < real_end;
+                    bits |= (uint32_t)(real ? Elem<T>::key(v, e) < pivot : vp < fp) << e;
+                }
+            }
+        }
+        return bits;
+    }
+
+    // Stable partition of group i; returns its predecessor count c_i.
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i) const
+    {
+        uint64_t pb = 0;
+#pragma unroll
+        for (int r = 0; r < NV; r++) {
+            const uint32_t bits = bits_of<FAST>(buf[r], r, i);
+            pb |= (uint64_t)bits << (r * V);
+            uint32_t tot = 0;
+#pragma unroll
+            for (int e = 0; e < V; e++)
+                tot += __popcll(__ballot((bits >> e) & 1));
+            if (lane == 0)
+                cnt[r * NW + wid] = tot;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            constexpr int C = (E + 63) / 64;
+            uint32_t x[C], sum = 0;
+#pragma unroll
+            for (int k = 0; k < C; k++) {
+                const int idx = lane * C + k;
+                x[k] = idx < E ? cnt[idx] : 0u;
+                sum += x[k];
+            }
+            uint32_t inc = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d, 64);
+                if (lane >= d)
+                    inc += y;
+            }
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int k = 0; k < C; k++) {
+                const int idx = lane * C + k;
+                if (idx < E)
+                    cnt[idx] = run;
+                run += x[k];
+            }
+            if (lane == 63)
+                cnt[E] = inc;
+        }
+        __syncthreads();
+        const uint32_t c = cnt[E];
+        const uint32_t b = 1u << log2b;
+#pragma unroll
+        for (int r = 0; r < NV; r++) {
+            const uint32_t q = r * NT + tid;
+            const uint32_t bits = (uint32_t)(pb >> (r * V)) & ((1u << V) - 1);
+            uint32_t rp = cnt[r * NW + wid];
+#pragma unroll
+            for (int e = 0; e < V; e++)
+                rp += lanes_below(__ballot((bits >> e) & 1));
+            uint64_t e0 = 0;
+            if (!FAST && q < nvec)
+                e0 = vec_start(q, i);
+#pragma unroll
+            for (int e = 0; e < V; e++) {
+                const bool p = (bits >> e) & 1;
+                const uint32_t slot = q * V + e;
+                const uint32_t d = p ? rp : c + slot - rp;
+                rp += p;
+                if (FAST || (q < nvec && e0 + e >= fp && e0 + e < real_end)) {
+                    const uint64_t vd = ((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1));
+                    store_elem<NTMP, T>(buf[r], e, elem_ptr(vd));
+                }
+            }
+        }
+        return c;
+    }
+};
+
+template <typename T, int NT, int NV, bool FIRST, bool NTMP, bool DB>
+__global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
+{
+    using Ctx = LevelCtx<T, NT, NV, NTMP>;
+    constexpr int W = Ctx::W;
+    constexpr int NW = Ctx::NW;
+    constexpr int MAXS = Ctx::NVEC * 16 / 64;  // lines of at least 64 bytes
+    static_assert(Ctx::E <= 256 && NV * Ctx::V <= 64, "tile shape");
+
+    __shared__ uint32_t xoff[MAXS];
+    __shared__ uint32_t cnt[Ctx::E + 1];
+    __shared__ uint64_t red[2 * NW];
+
+    const int tid = threadIdx.x;
+    const uint32_t bid = blockIdx.x;
+
+    uint64_t lo, hi;
+    if (FIRST) {
+        lo = a.lo;
+        hi = a.hi;
+    } else {
+        prev_region<NT>(a.prev, a.prev_count, a.prev_ctl, red, lo, hi);
+    }
+    if (!(lo < hi)) {
+        if (tid == 0) {
+            a.out[2 * bid] = bid == 0 ? lo : ~0ull;
+            a.out[2 * bid + 1] = bid == 0 ? lo : 0ull;
+            if (bid == 0) {
+                a.ctl[0] = lo; a.ctl[1] = lo; a.ctl[2] = 0; a.ctl[3] = 0;
+            }
+        }
+        return;
+    }
+
+    const Geo G = plan_geo((uintptr_t)a.base, lo, hi, W, a.log2b, a.s_max);
+    Ctx x;
+    x.g = G.g;
+    x.s = G.s;
+    x.fp = G.fp;
+    x.real_end = (uint64_t)G.fp + (hi - lo);
+    x.A0 = a.base + lo * W - (uint64_t)G.fp * W;
+    x.log2b = a.log2b;
+    x.vpl_log2 = a.log2b + Ctx::LOG2W - 4;
+    x.nvec = G.s << x.vpl_log2;
+    x.pivot = a.pivot;
+    x.xoff = xoff;
+    x.cnt = cnt;
+    x.tid = tid;
+    x.lane = tid & 63;
+    x.wid = tid >> 6;
+
+    if (bid == 0 && tid == 0) {
+        a.ctl[0] = lo; a.ctl[1] = hi; a.ctl[2] = G.g; a.ctl[3] = G.s;
+    }
+    for (uint32_t j = tid; j < G.s; j += NT)
+        xoff[j] = a.strided ? 0u : chunk_offset(a.seed, a.level, j, G.g);
+    __syncthreads();
+
+    uint64_t vmin = ~0ull, vmax = 0;
+    auto fold = [&](uint32_t c, uint32_t i) {
+        if (tid == 0) {
+            uint64_t vi;
+            if (c >= (G.s << x.log2b)) {
+                vi = hi;
+            } else {
+                const uint64_t vp =
+                    ((uint64_t)x.line_of(c >> x.log2b, i) << x.log2b) + (c & ((1u << x.log2b) - 1));
+                vi = vp >= x.real_end ? hi : lo + (vp - G.fp);
+            }
+            vmin = vi < vmin ? vi : vmin;
+            vmax = vi > vmax ? vi : vmax;
+        }
+    };
+    auto load_any = [&](v4u (&buf)[NV], uint32_t i) -> bool {
+        const bool f = x.fast(i);
+        if (f)
+            x.template load<true>(buf, i);
+        else
+            x.template load<false>(buf, i);
+        return f;
+    };
+    auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f) -> uint32_t {
+        return f ? x.template partition<true>(buf, i) : x.template partition<false>(buf, i);
+    };
+
+    const uint32_t step = gridDim.x;
+    // Workgroups are dispatched round-robin over the 8 XCDs; with order = 1 the
+    // groups a workgroup starts from are renumbered so that consecutive groups
+    // (adjacent lines of every chunk) run on the same XCD.
+    const uint32_t first = (a.order && (step & 7) == 0) ? (bid & 7) * (step >> 3) + (bid >> 3) : bid;
+    if (!DB) {
+        // One register buffer: the next group's loads are issued after this group's stores.
+        v4u buf[NV];
+        uint32_t i = first;
+        bool fast = false;
+        if (i < G.g)
+            fast = load_any(buf, i);
+        while (i < G.g) {
+            fold(part_any(buf, i, fast), i);
+            i += step;
+            if (i < G.g)
+                fast = load_any(buf, i);
+            __syncthreads();  // the counts are rewritten by the next group
+        }
+    } else {
+        // Two register buffers: the next group's loads are issued before this group is partitioned.
+        v4u ba[NV], bb[NV];
+        uint32_t i = first;
+        bool fa = false, fb = false;
+        if (i < G.g)
+            fa = load_any(ba, i);
+        while (i < G.g) {
+            if (i + step < G.g)
+                fb = load_any(bb, i + step);
+            fold(part_any(ba, i, fa), i);
+            __syncthreads();
+            i += step;
+            if (i >= G.g)
+                break;
+            if (i + step < G.g)
+                fa = load_any(ba, i + step);
+            fold(part_any(bb, i, fb), i);
+            __syncthreads();
+            i += step;
+        }
+    }
+    if (tid == 0) {
+        a.out[2 * bid] = vmin;
+        a.out[2 * bid + 1] = vmax;
+    }
+}
+
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
+{
+    if (first)
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, NTMP, DB>), dim3(grid), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, NTMP, DB>), dim3(grid), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+const void *level_rs_fn(bool first)
+{
+    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, NTMP, DB>)
+                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, NTMP, DB>);
+}
+
+#define SS_INSTANTIATE_RS(T, NT, NV, NTMP, DB)                                                              \
+    template hipError_t launch_level_rs<T, NT, NV, NTMP, DB>(bool, uint32_t, const LevelArgs &, hipStream_t); \
+    template const void *level_rs_fn<T, NT, NV, NTMP, DB>(bool);
+#define SS_INSTANTIATE_RS_ALL(NT, NV, NTMP, DB)   \
+    SS_INSTANTIATE_RS(uint32_t, NT, NV, NTMP, DB) \
+    SS_INSTANTIATE_RS(uint64_t, NT, NV, NTMP, DB) \
+    SS_INSTANTIATE_RS(KV, NT, NV, NTMP, DB)
+
+// single buffer: tiles of 32, 64 and 128 KiB; double buffer: 32 and 64 KiB
+SS_INSTANTIATE_RS_ALL(256, 8, false, false)
+SS_INSTANTIATE_RS_ALL(512, 8, false, false)
+SS_INSTANTIATE_RS_ALL(512, 16, false, false)
+SS_INSTANTIATE_RS_ALL(256, 8, true, false)
+SS_INSTANTIATE_RS_ALL(512, 8, true, false)
+SS_INSTANTIATE_RS_ALL(512, 16, true, false)
+SS_INSTANTIATE_RS_ALL(512, 4, false, true)
+SS_INSTANTIATE_RS_ALL(512, 8, false, true)
+SS_INSTANTIATE_RS_ALL(512, 4, true, true)
+SS_INSTANTIATE_RS_ALL(512, 8, true, true)
+
+}  // namespace ss

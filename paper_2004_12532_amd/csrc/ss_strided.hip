@@ -19,7 +19,8 @@ namespace ss {
 
 template <typename T, int NT, int BB>
 __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, const uint64_t *prev,
-                                                 uint32_t count, uint64_t *result, uint64_t *d_split)
+                                                 uint32_t count, uint64_t *result, uint64_t *d_split,
+                                                 const uint64_t *ctl, uint64_t *host)
 {
     constexpr int W = sizeof(T);
     constexpr int B = BB / W;      // elements per block
@@ -166,25 +167,33 @@ __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, cons
         result[1] = L + tot;
         if (d_split)
             *d_split = L + tot;
+        if (host) {
+            host[0] = 1;
+            host[1] = L + tot;
+            host[2] = lo;
+            host[3] = hi;
+        }
     }
+    if (host && tid < kCtlWords)
+        host[kResultWordsDev + tid] = ctl[tid];
 }
 
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
-                          uint64_t *result, uint64_t *d_split, hipStream_t st)
+                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint64_t *host, hipStream_t st)
 {
     constexpr int NT = 1024, BB = 16384;
     switch (dtype) {
     case SS_U32:
         hipLaunchKernelGGL((k_cleanup<uint32_t, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count,
-                           result, d_split);
+                           result, d_split, ctl, host);
         break;
     case SS_U64:
         hipLaunchKernelGGL((k_cleanup<uint64_t, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count,
-                           result, d_split);
+                           result, d_split, ctl, host);
         break;
     default:
         hipLaunchKernelGGL((k_cleanup<KV, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count, result,
-                           d_split);
+                           d_split, ctl, host);
         break;
     }
     return hipGetLastError();

@@ -50,12 +50,13 @@ def test_argument_validation_without_device():
     assert L.ss_partition(ctypes.c_void_p(0x1000), 10, 9, 5, ctypes.byref(split)) == -1  # bad dtype
     assert L.ss_partition(ctypes.c_void_p(0x1000), 10, ss.SS_U64, 5, None) == -1        # no split out
     for bad in (ss.make_params(b=3), ss.make_params(b=4), ss.make_params(b=1024), ss.make_params(tile_bytes=4096),
-                ss.make_params(max_levels=33), ss.make_params(algo=7)):
+                ss.make_params(max_levels=33), ss.make_params(algo=7),
+                ss.make_params(engine="lds", tile_bytes=131072)):
         rc = L.ss_partition_ex(ctypes.c_void_p(0x1000), 10, ss.SS_U64, 5, ctypes.byref(bad), None, None,
                                ctypes.byref(split), None)
         assert rc == -1, (bad.b, bad.tile_bytes, bad.max_levels, bad.algo)
     bad = ss.make_params()
-    bad.reserved = 1
+    bad.engine = 9
     assert L.ss_partition_ex(ctypes.c_void_p(0x1000), 10, ss.SS_U64, 5, ctypes.byref(bad), None, None,
                              ctypes.byref(split), None) == -1
     assert split.value == 7  # untouched on argument errors

@@ -66,8 +66,12 @@ def test_config1_median_u64(ss):
 SIZES = [1, 2, 3, 15, 16, 17, 31, 127, 128, 129, 1000, 8191, 8192, 8193, 16385, 65535, 65537, 100003, 300001]
 
 
+ENGINES = ["lds", "regs", "regs2"]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
-def test_shapes_and_pivots(ss, kind):
+def test_shapes_and_pivots(ss, kind, engine):
     for n in SIZES:
         a0 = gen(kind, n, 1000 + n)
         keys = a0[:, 0] if a0.ndim == 2 else a0
@@ -77,7 +81,7 @@ def test_shapes_and_pivots(ss, kind):
         if kind == "u32":
             pivots |= {1 << 32, (1 << 32) - 1}
         for p in sorted(pivots):
-            check_against_oracle(ss, a0, p)
+            check_against_oracle(ss, a0, p, engine=engine)
 
 
 @pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
@@ -101,15 +105,15 @@ def test_duplicates_and_structured_inputs(ss, kind):
             check_against_oracle(ss, a0, workloads.pivot_at_quantile_np(a0, q))
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
-def test_unaligned_subarrays(ss, kind):
+def test_unaligned_subarrays(ss, kind, engine):
     # Sub-tensors starting at every element offset inside a 128-byte line.
     torch = _torch()
     n = 50000
     full = gen(kind, n + 64, 77)
     t_full = to_device(full)
-    step = {"u32": 1, "u64": 1, "kv": 1}[kind]
-    for off in range(0, 33, step):
+    for off in range(0, 33):
         if off + 1000 > n:
             break
         length = n - off - (off * 37) % 500
@@ -118,7 +122,7 @@ def test_unaligned_subarrays(ss, kind):
         t = t_full.clone()
         view = t[off:off + length]
         assert view.is_contiguous()
-        split = ss.partition(view, p)
+        split = ss.partition(view, p, engine=engine)
         out = to_host(t, full)
         # outside the sub-array nothing changed
         assert np.array_equal(out[:off], full[:off]) and np.array_equal(out[off + length:], full[off + length:])
@@ -137,16 +141,17 @@ def _group_of_position(n, b, g, s, X):
     return np.repeat(grp, b)[:n]
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
 @pytest.mark.parametrize("algo", ["smoothed", "strided"])
-def test_one_level_matches_oracle_level(ss, kind, algo):
+def test_one_level_matches_oracle_level(ss, kind, algo, engine):
     """One Partial Partition Step: (v_min, v_max), the side of every position and
     the multiset of every group equal the oracle's step with the same offsets."""
     for n, seed, q in ((1 << 18, 1, 0.5), (123457, 2, 0.1), (300000, 3, 0.9), (40000, 4, 0.5)):
         a0 = gen(kind, n, seed)
         p = workloads.pivot_at_quantile_np(a0, q)
         t = to_device(a0)
-        split, st = ss.partition(t, p, stats=True, one_level=True, algo=algo, seed=1234 + seed)
+        split, st = ss.partition(t, p, stats=True, one_level=True, algo=algo, seed=1234 + seed, engine=engine)
         out = to_host(t, a0)
         g, s, b = st["level_g"][0], st["level_s"][0], st["b"]
         assert st["level_lo"][0] == 0 and st["level_hi"][0] == n
@@ -177,15 +182,31 @@ def test_same_seed_same_bytes_and_other_seeds_correct(ss):
         check_against_oracle(ss, a0, p, seed=sd)
 
 
-@pytest.mark.parametrize("tile", [32768, 65536])
+@pytest.mark.parametrize("engine,tile", [("lds", 32768), ("lds", 65536), ("regs", 32768), ("regs", 65536),
+                                         ("regs", 131072), ("regs2", 32768), ("regs2", 65536)])
 @pytest.mark.parametrize("line_bytes", [64, 128, 256, 512, 1024, 4096])
-def test_tiles_and_line_sizes(ss, tile, line_bytes):
+def test_tiles_and_line_sizes(ss, engine, tile, line_bytes):
     for kind, w in (("u32", 4), ("u64", 8), ("kv", 16)):
         if line_bytes > tile:
             continue
         a0 = gen(kind, 200003, line_bytes + w)
         p = workloads.pivot_at_quantile_np(a0, 0.37)
-        check_against_oracle(ss, a0, p, b=line_bytes // w, tile_bytes=tile)
+        check_against_oracle(ss, a0, p, b=line_bytes // w, tile_bytes=tile, engine=engine)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_engines_give_identical_bytes(ss, kind):
+    """Every workgroup body computes the same stable partition of every group."""
+    for n, q, tile in ((1 << 20, 0.5, 32768), (777777, 0.05, 65536), (3001, 0.5, 32768)):
+        a0 = gen(kind, n, 55 + n)
+        p = workloads.pivot_at_quantile_np(a0, q)
+        t1 = to_device(a0)
+        s1 = ss.partition(t1, p, engine="lds", tile_bytes=tile, seed=5)
+        for engine, stream in (("regs", False), ("regs", True), ("regs2", False), ("regs2", True)):
+            t2 = to_device(a0)
+            s2 = ss.partition(t2, p, engine=engine, tile_bytes=tile, seed=5, stream=stream)
+            assert s1 == s2
+            assert bool((t1 == t2).all()), (engine, stream)
 
 
 def test_small_level_budget_continues_from_host(ss):
