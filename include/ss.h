@@ -81,7 +81,10 @@ enum ss_status {
 /* Flags for ss_params.flags. */
 #define SS_FLAG_ONE_LEVEL 1u   /* run only the first Partial Partition Step; the array is then only
                                   partially partitioned: [0, v_min) predecessors, [v_max, n)
-                                  successors, reported in ss_stats (Section 4).  For tests. */
+                                  successors, reported in ss_stats (Section 4).  With SS_LOWSPACE:
+                                  stop after the preprocessing phase (Section 3); ss_stats.vmin is
+                                  then the predecessor count and ss_stats.vmax is 1 if the roles
+                                  were swapped (the array is read reversed).  For tests. */
 #define SS_FLAG_TIME 2u        /* time the first-level kernel and the whole call with HIP events on
                                   the call's stream; reported in ss_stats (synchronizes). */
 #define SS_FLAG_STREAM 4u      /* register engines: non-temporal (streaming) loads and stores */

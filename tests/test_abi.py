@@ -71,4 +71,5 @@ def test_strerror_and_aux_bytes():
     assert small < (1 << 22)                                   # polylog-sized workspace
     assert small == ss.aux_bytes(1 << 20, ss.SS_U64, "smoothed")
     ls = ss.aux_bytes(1 << 30, ss.SS_U64, "lowspace")
-    assert ls - small >= (1 << 30) // 32 * 8                   # explicit block-count array ~ n/32 words
+    assert ls - small >= (1 << 30) // 64 * 4                   # one 32-bit block prefix per 64 elements
+    assert ls - small < (1 << 30) // 64 * 4 + (1 << 20)
