@@ -313,7 +313,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             a.s_max = tail ? s_max_t : R.s_max;
             uint32_t grid = tail ? Pt : P;
             if (first) {
-                const Geo G = plan_geo((uintptr_t)base, lo, hi, R.w, a.log2b, a.s_max);
+                const Geo G = plan_geo(lo, hi, a.log2b, a.s_max);
                 grid = G.g < grid ? G.g : grid;
                 a.lo = lo;
                 a.hi = hi;

@@ -1,6 +1,421 @@
-// ss_batched.hip -- batched partition of many arrays (placeholder until its
-// kernels land: reports SS_EUNSUPPORTED).
+// ss_batched.hip -- Smoothed Striding partition of many independent arrays
+// with one persistent launch per recursion level (Section 4's Partial
+// Partition Step applied to every array at once).
+//
+// Device state, one entry per array k: its current region [lo_k, hi_k)
+// (absolute element indices into the base), its pivot, its number of groups
+// g_k at this level, and its split once found.  A level is four launches with
+// no host decision in between:
+//   k_bplan   per array: the level's geometry g_k from its region;
+//   k_bscan   one workgroup: exclusive scan of g_k -> the array's first item;
+//   k_bfill   item map: item t -> array k (one wavefront per array);
+//   k_blevel  persistent: every workgroup takes items t = bid, bid + grid, ...,
+//             partitions group t - first_k of array k exactly as the
+//             single-array kernel does and writes the group's splitting
+//             position v;
+//   k_breduce per array: [v_min, v_max) over its items; a region left with
+//             one group or none is finished (split = v_min); otherwise it is
+//             the next level's region.
+// Arrays that fit one group are whole-array tiles (g = 1) and finish at the
+// first level.  The chunk offsets depend on (seed, level, j, g) only, never on
+// an array's position in the batch, so an array gets the same bytes alone and
+// inside any batch.
+#include "ss_common.h"
+#include "ss_device.h"
 #include "ss_internal.h"
+#include "ss_levelctx.h"
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace ss {
+
+struct BatchState {
+    uint64_t *start;   // first element of array k
+    uint64_t *len;     // its length
+    const uint64_t *pivot;
+    uint64_t *lo, *hi; // current region (absolute)
+    uint64_t *split;   // absolute split, ~0 while open
+    uint32_t *g;       // groups at the current level (0: finished)
+    uint64_t *first;   // first item of array k at the current level (num + 1 entries)
+    uint32_t *imap;    // item -> array
+    uint64_t *vout;    // item -> splitting position
+    uint64_t *ctl;     // [0] items of the current level, [1] open arrays
+    uint32_t num;
+};
+
+struct BatchGeom {
+    char *base;
+    uint32_t w, log2b, s_max;
+    uint64_t seed;
+    uint32_t level;
+};
+
+__global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= B.num)
+        return;
+    const uint64_t s = B.start[k], l = B.len[k];
+    B.lo[k] = s;
+    B.hi[k] = s + l;
+    B.split[k] = l ? ~0ull : s;
+}
+
+__global__ void __launch_bounds__(256) k_bplan(BatchState B, BatchGeom Gm)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= B.num)
+        return;
+    uint32_t g = 0;
+    if (B.split[k] == ~0ull) {
+        const Geo G = plan_geo(B.lo[k] - B.start[k], B.hi[k] - B.start[k], Gm.log2b, Gm.s_max);
+        g = G.g;
+    }
+    B.g[k] = g;
+}
+
+__global__ void __launch_bounds__(1024) k_bscan(BatchState B)
+{
+    __shared__ uint64_t wsum[16], wopen[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t per = (B.num + 1023) / 1024;
+    const uint32_t k0 = threadIdx.x * per;
+    uint64_t s = 0, open = 0;
+    for (uint32_t k = k0; k < k0 + per && k < B.num; k++) {
+        s += B.g[k];
+        open += B.g[k] != 0;
+    }
+    uint64_t inc = s, oinc = open;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, 64), z = __shfl_up(oinc, d, 64);
+        if (lane >= d) {
+            inc += y;
+            oinc += z;
+        }
+    }
+    if (lane == 63) {
+        wsum[wid] = inc;
+        wopen[wid] = oinc;
+    }
+    __syncthreads();
+    uint64_t off = 0, ooff = 0;
+    for (int w = 0; w < wid; w++) {
+        off += wsum[w];
+        ooff += wopen[w];
+    }
+    uint64_t run = off + inc - s;
+    for (uint32_t k = k0; k < k0 + per && k < B.num; k++) {
+        B.first[k] = run;
+        run += B.g[k];
+    }
+    if (threadIdx.x == 1023) {
+        B.first[B.num] = run;
+        B.ctl[0] = run;
+        B.ctl[1] = ooff + oinc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bfill(BatchState B)
+{
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= B.num)
+        return;
+    const uint64_t f = B.first[k];
+    const uint32_t g = B.g[k];
+    for (uint32_t i = threadIdx.x & 63; i < g; i += 64)
+        B.imap[f + i] = k;
+}
+
+template <typename T, int NT, int NV>
+__global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
+{
+    using Ctx = LevelCtx<T, NT, NV>;
+    constexpr int W = Ctx::W;
+    constexpr int MAXS = Ctx::NVEC * 16 / 64;
+    __shared__ uint32_t xoff[MAXS];
+    __shared__ uint32_t cnt[Ctx::E + 1];
+
+    const int tid = threadIdx.x;
+    const uint64_t total = B.ctl[0];
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t k = B.imap[t];
+        const uint32_t i = (uint32_t)(t - B.first[k]);
+        const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
+        const Geo G = plan_geo(lo - start, hi - start, Gm.log2b, Gm.s_max);
+        Ctx x;
+        x.g = G.g;
+        x.s = G.s;
+        x.fp = G.fp;
+        x.real_end = (uint64_t)G.fp + (hi - lo);
+        x.A0 = Gm.base + (lo - G.fp) * W;  // line grid counted from the array's first element
+        x.log2b = Gm.log2b;
+        x.vpl_log2 = Gm.log2b + Ctx::LOG2W - 4;
+        x.nvec = G.s << x.vpl_log2;
+        x.pivot = B.pivot[k];
+        x.xoff = xoff;
+        x.cnt = cnt;
+        x.tid = tid;
+        x.lane = tid & 63;
+        x.wid = tid >> 6;
+        for (uint32_t j = tid; j < G.s; j += NT)
+            xoff[j] = G.g > 1 ? chunk_offset(Gm.seed, Gm.level, j, G.g) : 0u;
+        __syncthreads();
+        v4u buf[NV];
+        const bool fast = x.fast(i);
+        uint32_t c;
+        if (fast) {
+            x.template load<true>(buf, i);
+            c = x.template partition<true>(buf, i);
+        } else {
+            x.template load<false>(buf, i);
+            c = x.template partition<false>(buf, i);
+        }
+        if (tid == 0) {
+            uint64_t vi;
+            if (c >= (G.s << Gm.log2b)) {
+                vi = hi;
+            } else {
+                const uint64_t vp =
+                    ((uint64_t)x.line_of(c >> Gm.log2b, i) << Gm.log2b) + (c & ((1u << Gm.log2b) - 1));
+                vi = vp >= x.real_end ? hi : lo + (vp - G.fp);
+            }
+            B.vout[t] = vi;
+        }
+        __syncthreads();  // LDS reused by the next item
+    }
+}
+
+__global__ void __launch_bounds__(256) k_breduce(BatchState B)
+{
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= B.num)
+        return;
+    const uint32_t g = B.g[k];
+    if (g == 0)
+        return;
+    const uint64_t f = B.first[k];
+    uint64_t mn = ~0ull, mx = 0;
+    for (uint32_t i = threadIdx.x & 63; i < g; i += 64) {
+        const uint64_t v = B.vout[f + i];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) {
+        if (g == 1 || !(mn < mx)) {
+            B.split[k] = mn;
+        } else {
+            B.lo[k] = mn;
+            B.hi[k] = mx;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bfinish(BatchState B, uint64_t *d_splits)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= B.num)
+        return;
+    const uint64_t s = B.split[k];
+    d_splits[k] = s == ~0ull ? ~0ull : s - B.start[k];
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+struct BatchWork {
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    uint64_t *host = nullptr;  // pinned staging for start/len
+    size_t host_words = 0;
+};
+std::mutex g_b_mu;
+std::map<std::pair<int, void *>, BatchWork> g_b;
+
+template <typename T, int NT, int NV>
+hipError_t launch_blevel(uint32_t grid, const BatchState &B, const BatchGeom &G, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_blevel<T, NT, NV>), dim3(grid), dim3(NT), 0, st, B, G);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int NV>
+const void *blevel_fn()
+{
+    return reinterpret_cast<const void *>(&k_blevel<T, NT, NV>);
+}
+
+struct BVariant {
+    int dtype;
+    uint32_t tile;
+    int nt;
+    hipError_t (*launch)(uint32_t, const BatchState &, const BatchGeom &, hipStream_t);
+    const void *(*fn)();
+};
+
+#define SS_BV(D, T, NT, NV) {D, NT * NV * 16, NT, &launch_blevel<T, NT, NV>, &blevel_fn<T, NT, NV>}
+
+const BVariant *pick_bvariant(int dtype, uint32_t tile)
+{
+    static const BVariant v[] = {
+        SS_BV(SS_U32, uint32_t, 256, 8),  SS_BV(SS_U64, uint64_t, 256, 8),  SS_BV(SS_KV16, KV, 256, 8),
+        SS_BV(SS_U32, uint32_t, 512, 8),  SS_BV(SS_U64, uint64_t, 512, 8),  SS_BV(SS_KV16, KV, 512, 8),
+        SS_BV(SS_U32, uint32_t, 512, 16), SS_BV(SS_U64, uint64_t, 512, 16), SS_BV(SS_KV16, KV, 512, 16),
+    };
+    for (const BVariant &x : v)
+        if (x.dtype == dtype && x.tile == tile)
+            return &x;
+    return nullptr;
+}
+
+}  // namespace
+
+// Run the batched recursion for `num` arrays whose start/len are already in
+// device memory (B.start, B.len).  Writes d_splits (relative to each start,
+// UINT64_MAX if unfinished).  When `sync`, continues from the host until every
+// array is finished and fills *open_left with 0.
+int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64_t items_cap, hipStream_t st,
+                 uint64_t *d_splits, bool sync, uint32_t *launches, uint32_t *levels_run)
+{
+    (void)items_cap;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    int cus = 0, lds = 0;
+    int rc = device_info(dev, &cus, &lds);
+    if (rc)
+        return rc;
+    Workspace *ws = nullptr;
+    if ((rc = get_workspace(dev, st, &ws)))
+        return rc;
+    const uint32_t tile = R.engine == SS_ENGINE_REGS && R.tile ? R.tile : 131072u;
+    const BVariant *V = pick_bvariant(dtype, tile);
+    if (!V)
+        return fail_msg(SS_EUNSUPPORTED, "no batched kernel variant for dtype/tile");
+    int occ = 0;
+    if ((rc = occupancy(dev, V->fn(), V->nt, &occ)))
+        return rc;
+    uint32_t P = (uint32_t)(occ * cus);
+    BatchGeom Gm;
+    Gm.base = base;
+    Gm.w = R.w;
+    Gm.log2b = R.log2b;
+    Gm.s_max = (uint32_t)(tile / ((uint64_t)R.b * R.w));
+    Gm.seed = R.seed;
+    const uint32_t nb256 = (B.num + 255) / 256, nb4 = (B.num + 3) / 4;
+    hipLaunchKernelGGL(k_binit, dim3(nb256), dim3(256), 0, st, B, Gm);
+    (*launches)++;
+    uint32_t level = 0;
+    for (;;) {
+        for (uint32_t k = 0; k < R.levels; k++, level++) {
+            Gm.level = level;
+            hipLaunchKernelGGL(k_bplan, dim3(nb256), dim3(256), 0, st, B, Gm);
+            hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, B);
+            hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
+            if ((e = V->launch(P, B, Gm, st)) != hipSuccess)
+                return fail_device(e, "batched level launch");
+            hipLaunchKernelGGL(k_breduce, dim3(nb4), dim3(256), 0, st, B);
+            *launches += 5;
+        }
+        *levels_run = level;
+        // open arrays after the last reduce: plan once more to count them
+        Gm.level = level;
+        hipLaunchKernelGGL(k_bplan, dim3(nb256), dim3(256), 0, st, B, Gm);
+        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, B);
+        *launches += 2;
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail_device(e, "batched launch");
+        if (!sync)
+            break;
+        if ((e = hipMemcpyAsync(ws->host, B.ctl, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return fail_device(e, "hipMemcpyAsync");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return fail_device(e, "hipStreamSynchronize");
+        if (((volatile uint64_t *)ws->host)[1] == 0)
+            break;
+        if (level >= kHostLevelCap)
+            return fail_msg(SS_EDEVICE, "batched recursion did not converge");
+    }
+    if (d_splits) {
+        hipLaunchKernelGGL(k_bfinish, dim3(nb256), dim3(256), 0, st, B, d_splits);
+        (*launches)++;
+    }
+    if ((e = hipGetLastError()) != hipSuccess)
+        return fail_device(e, "batched finish launch");
+    return SS_OK;
+}
+
+// Device state for `num` arrays (grown on demand, per device and stream).
+int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage)
+{
+    std::lock_guard<std::mutex> lk(g_b_mu);
+    BatchWork &w = g_b[std::make_pair(dev, stream)];
+    const size_t words = 8 + (size_t)num * 6 + (num + 1) + items_cap + (items_cap + 1) / 2 + (size_t)(num + 1) / 2 + 16;
+    const size_t bytes = words * sizeof(uint64_t);
+    hipError_t e;
+    if (w.dev_bytes < bytes) {
+        if (w.dev)
+            (void)hipFree(w.dev);
+        w.dev = nullptr;
+        w.dev_bytes = 0;
+        if ((e = hipMalloc((void **)&w.dev, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_msg(SS_ENOMEM, std::string("batched state hipMalloc: ") + hipGetErrorString(e));
+        }
+        w.dev_bytes = bytes;
+    }
+    const size_t hwords = 2 * (size_t)num + 2;
+    if (w.host_words < hwords) {
+        if (w.host)
+            (void)hipHostFree(w.host);
+        w.host = nullptr;
+        w.host_words = 0;
+        if ((e = hipHostMalloc((void **)&w.host, hwords * sizeof(uint64_t), hipHostMallocDefault)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_msg(SS_ENOMEM, std::string("batched staging hipHostMalloc: ") + hipGetErrorString(e));
+        }
+        w.host_words = hwords;
+    }
+    uint64_t *p = reinterpret_cast<uint64_t *>(w.dev);
+    B->ctl = p;
+    p += 8;
+    B->start = p;
+    p += num;
+    B->len = p;
+    p += num;
+    B->lo = p;
+    p += num;
+    B->hi = p;
+    p += num;
+    B->split = p;
+    p += num;
+    B->first = p;
+    p += num + 1;
+    B->vout = p;
+    p += items_cap;
+    B->g = reinterpret_cast<uint32_t *>(p);
+    p += (num + 1) / 2 + 1;
+    B->imap = reinterpret_cast<uint32_t *>(p);
+    B->num = num;
+    *host_stage = w.host;
+    return SS_OK;
+}
+
+uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems)
+{
+    uint64_t cap = 64;
+    for (uint32_t k = 0; k < num; k++)
+        cap += lens[k] / tile_elems + 3;
+    return cap;
+}
+
+}  // namespace ss
 
 using namespace ss;
 
@@ -8,7 +423,89 @@ extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, siz
                                     const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                                     void *stream, ss_stats *stats)
 {
-    (void)d_base; (void)h_offsets; (void)num; (void)dtype; (void)d_pivots; (void)d_splits; (void)p;
-    (void)stream; (void)stats;
-    return fail_msg(SS_EUNSUPPORTED, "batched partition not available");
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    if (num == 0)
+        return SS_OK;
+    if (!h_offsets || !d_pivots || !d_splits)
+        return fail_msg(SS_EINVAL, "null offsets, pivots or splits");
+    if (num > (1u << 30))
+        return fail_msg(SS_EINVAL, "too many arrays");
+    for (size_t k = 0; k < num; k++)
+        if (h_offsets[k + 1] < h_offsets[k])
+            return fail_msg(SS_EINVAL, "offsets must be non-decreasing");
+    const uint64_t total = h_offsets[num];
+    int rc = check_array(d_base, (size_t)total, dtype);
+    if (rc)
+        return rc;
+    if (((uintptr_t)d_splits % 8) || ((uintptr_t)d_pivots % 8))
+        return fail_msg(SS_EINVAL, "pivots and splits must be 8-byte aligned");
+    Resolved R;
+    if ((rc = resolve_params(p, dtype, &R)))
+        return rc;
+    if (R.algo != SS_SMOOTHED)
+        return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
+    if (R.engine != SS_ENGINE_REGS)
+        return fail_msg(SS_EUNSUPPORTED, "batched partition uses the register engine");
+    if (!p || !p->max_levels)
+        R.levels = 6;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    std::vector<uint64_t> lens(num);
+    for (size_t k = 0; k < num; k++)
+        lens[k] = h_offsets[k + 1] - h_offsets[k];
+    const uint64_t items_cap = batched_items_cap(lens.data(), (uint32_t)num, R.tile / R.w);
+    BatchState B;
+    uint64_t *stage = nullptr;
+    if ((rc = batched_state(dev, stream, (uint32_t)num, items_cap, &B, &stage)))
+        return rc;
+    B.pivot = d_pivots;
+    // the previous call on this stream may still read the staging buffer
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return fail_device(e, "hipStreamSynchronize");
+    std::memcpy(stage, h_offsets, num * sizeof(uint64_t));
+    std::memcpy(stage + num, lens.data(), num * sizeof(uint64_t));
+    if ((e = hipMemcpyAsync(B.start, stage, 2 * num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail_device(e, "hipMemcpyAsync");
+    RunOut ro;
+    std::memset(&ro, 0, sizeof(ro));
+    const bool sync = stats != nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    const bool timing = (R.flags & SS_FLAG_TIME) != 0;
+    if (timing) {
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+            return fail_msg(SS_EDEVICE, "hipEventCreate");
+        (void)hipEventRecord(t0, st);
+    }
+    uint32_t levels_run = 0;
+    rc = batched_core((char *)d_base, dtype, R, B, items_cap, st, d_splits, sync || timing, &ro.launches,
+                      &levels_run);
+    if (rc)
+        return rc;
+    if (timing) {
+        (void)hipEventRecord(t1, st);
+        (void)hipEventSynchronize(t1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ro.total_ms = ms;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    }
+    if (stats) {
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return fail_device(e, "hipStreamSynchronize");
+        ro.levels_run = 0;
+        fill_stats(stats, ro, R, dtype);
+        stats->levels = levels_run;
+        stats->aux_bytes = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_b_mu);
+            stats->aux_bytes = g_b[std::make_pair(dev, stream)].dev_bytes;
+        }
+    }
+    return SS_OK;
 }

@@ -2,8 +2,9 @@
 //
 // Geometry of one Partial Partition Step (Section 4, "Formal Algorithm
 // Description"): the region [lo, hi) of the array is viewed as lines of b
-// elements anchored at absolute (b * sizeof(element))-byte boundaries.  If
-// the region does not start on such a boundary, the fp elements between the
+// elements counted from the array's first element (so an array's result
+// depends only on its contents, never on where it sits in memory).  If the
+// region does not start on a line boundary, the fp elements between the
 // boundary and lo are treated as virtual predecessors (they precede the
 // region, where everything is already a predecessor, and are never read or
 // written); past hi the padding up to s*g*b elements is made of virtual
@@ -53,13 +54,12 @@ struct Geo {
     uint32_t fp;  // virtual predecessors in front of the region
 };
 
-__host__ __device__ __forceinline__ Geo plan_geo(uintptr_t base, uint64_t lo, uint64_t hi, uint32_t w,
-                                                 uint32_t log2b, uint32_t s_max)
+// Geometry of the region [lo, hi) of an array whose lines start at its
+// element 0 (lo and hi relative to the array's first element).
+__host__ __device__ __forceinline__ Geo plan_geo(uint64_t lo, uint64_t hi, uint32_t log2b, uint32_t s_max)
 {
     Geo G;
-    const uint64_t line_bytes = (uint64_t)w << log2b;
-    const uintptr_t start = base + lo * w;
-    G.fp = (uint32_t)((start & (line_bytes - 1)) / w);
+    G.fp = (uint32_t)(lo & ((1ull << log2b) - 1));
     G.nv = (hi - lo) + G.fp;
     G.L = (G.nv + (1ull << log2b) - 1) >> log2b;
     const uint64_t g = (G.L + s_max - 1) / s_max;

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(NT) k_level(const LevelArgs a)
 
     const uint32_t log2b = a.log2b;
     const uint32_t b = 1u << log2b;
-    const Geo G = plan_geo((uintptr_t)a.base, lo, hi, W, log2b, a.s_max);
+    const Geo G = plan_geo(lo, hi, log2b, a.s_max);
     const uint32_t g = G.g, s = G.s, fp = G.fp;
     const uint64_t real_end = (uint64_t)fp + (hi - lo);  // virtual index past the last real element
     char *const A0 = a.base + lo * W - (uint64_t)fp * W; // line-aligned anchor

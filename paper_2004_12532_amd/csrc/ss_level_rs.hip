@@ -28,198 +28,9 @@
 #include "ss_common.h"
 #include "ss_device.h"
 #include "ss_internal.h"
+#include "ss_levelctx.h"
 
 namespace ss {
-
-template <bool NTMP>
-__device__ __forceinline__ v4u load_vec(const char *p)
-{
-    if (NTMP)
-        return __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
-    return *reinterpret_cast<const v4u *>(p);
-}
-
-template <bool NTMP, typename T>
-__device__ __forceinline__ void store_elem(const v4u &v, int e, char *p)
-{
-    if (NTMP) {
-        if constexpr (sizeof(T) == 4) {
-            __builtin_nontemporal_store(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w, reinterpret_cast<uint32_t *>(p));
-        } else if constexpr (sizeof(T) == 8) {
-            typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-            const v2u x = e == 0 ? v2u{v.x, v.y} : v2u{v.z, v.w};
-            __builtin_nontemporal_store(x, reinterpret_cast<v2u *>(p));
-        } else {
-            __builtin_nontemporal_store(v, reinterpret_cast<v4u *>(p));
-        }
-    } else {
-        Elem<T>::store1(v, e, p);
-    }
-}
-
-template <typename T, int NT, int NV, bool NTMP = false>
-struct LevelCtx {
-    static constexpr int W = sizeof(T);
-    static constexpr int LOG2W = W == 4 ? 2 : W == 8 ? 3 : 4;
-    static constexpr int V = Elem<T>::V;
-    static constexpr int NW = NT / 64;
-    static constexpr int NVEC = NT * NV;
-    static constexpr int E = NV * NW;  // (round, wave) counts
-
-    char *A0;           // line-aligned anchor of the region
-    const uint32_t *xoff;
-    uint32_t *cnt;      // E + 1 words of LDS
-    uint64_t pivot;
-    uint64_t real_end;  // virtual index past the last real element
-    uint32_t fp;        // virtual predecessors in front
-    uint32_t g, s;
-    uint32_t log2b, vpl_log2, nvec;
-    int tid, lane, wid;
-
-    __device__ __forceinline__ uint32_t line_of(uint32_t j, uint32_t i) const
-    {
-        uint32_t r = xoff[j] + i;
-        r = r >= g ? r - g : r;
-        return j * g + r;
-    }
-    __device__ __forceinline__ uint64_t vec_start(uint32_t q, uint32_t i) const
-    {
-        return ((uint64_t)line_of(q >> vpl_log2, i) << log2b) + (q & ((1u << vpl_log2) - 1)) * V;
-    }
-    __device__ __forceinline__ char *elem_ptr(uint64_t vpos) const { return A0 + (vpos << LOG2W); }
-
-    // Every slot of group i is a real element and the group fills the tile.
-    __device__ __forceinline__ bool fast(uint32_t i) const
-    {
-        if (nvec != (uint32_t)NVEC)
-            return false;
-        if (fp && line_of(0, i) == 0)
-            return false;
-        return ((uint64_t)(line_of(s - 1, i) + 1) << log2b) <= real_end;
-    }
-
-    template <bool FAST>
-    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i) const
-    {
-#pragma unroll
-        for (int r = 0; r < NV; r++) {
-            const uint32_t q = r * NT + tid;
-            if (FAST) {
-                buf[r] = load_vec<NTMP>(elem_ptr(vec_start(q, i)));
-            } else {
-                buf[r] = v4u{0u, 0u, 0u, 0u};
-                if (q < nvec) {
-                    const uint64_t e0 = vec_start(q, i);
-                    if (e0 >= fp && e0 + V <= real_end) {
-                        buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(e0));
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < V; e++)
-                            if (e0 + e >= fp && e0 + e < real_end)
-                                Elem<T>::load1(buf[r], e, elem_ptr(e0 + e));
-                    }
-                }
-            }
-        }
-    }
-
-    // Decider bits of vector r; virtual front elements count as predecessors.
-    template <bool FAST>
-    __device__ __forceinline__ uint32_t bits_of(const v4u &v, int r, uint32_t i) const
-    {
-        uint32_t bits = 0;
-        if (FAST) {
-#pragma unroll
-            for (int e = 0; e < V; e++)
-                bits |= (uint32_t)(Elem<T>::key(v, e) < pivot) << e;
-        } else {
-            const uint32_t q = r * NT + tid;
-            if (q < nvec) {
-                const uint64_t e0 = vec_start(q, i);
-#pragma unroll
-                for (int e = 0; e < V; e++) {
-                    const uint64_t vp = e0 + e;
-                    const bool real = vp >= fp && vp < real_end;
-                    bits |= (uint32_t)(real ? Elem<T>::key(v, e) < pivot : vp < fp) << e;
-                }
-            }
-        }
-        return bits;
-    }
-
-    // Stable partition of group i; returns its predecessor count c_i.
-    template <bool FAST>
-    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i) const
-    {
-        uint64_t pb = 0;
-#pragma unroll
-        for (int r = 0; r < NV; r++) {
-            const uint32_t bits = bits_of<FAST>(buf[r], r, i);
-            pb |= (uint64_t)bits << (r * V);
-            uint32_t tot = 0;
-#pragma unroll
-            for (int e = 0; e < V; e++)
-                tot += __popcll(__ballot((bits >> e) & 1));
-            if (lane == 0)
-                cnt[r * NW + wid] = tot;
-        }
-        __syncthreads();
-        if (wid == 0) {
-            constexpr int C = (E + 63) / 64;
-            uint32_t x[C], sum = 0;
-#pragma unroll
-            for (int k = 0; k < C; k++) {
-                const int idx = lane * C + k;
-                x[k] = idx < E ? cnt[idx] : 0u;
-                sum += x[k];
-            }
-            uint32_t inc = sum;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t y = __shfl_up(inc, d, 64);
-                if (lane >= d)
-                    inc += y;
-            }
-            uint32_t run = inc - sum;
-#pragma unroll
-            for (int k = 0; k < C; k++) {
-                const int idx = lane * C + k;
-                if (idx < E)
-                    cnt[idx] = run;
-                run += x[k];
-            }
-            if (lane == 63)
-                cnt[E] = inc;
-        }
-        __syncthreads();
-        const uint32_t c = cnt[E];
-        const uint32_t b = 1u << log2b;
-#pragma unroll
-        for (int r = 0; r < NV; r++) {
-            const uint32_t q = r * NT + tid;
-            const uint32_t bits = (uint32_t)(pb >> (r * V)) & ((1u << V) - 1);
-            uint32_t rp = cnt[r * NW + wid];
-#pragma unroll
-            for (int e = 0; e < V; e++)
-                rp += lanes_below(__ballot((bits >> e) & 1));
-            uint64_t e0 = 0;
-            if (!FAST && q < nvec)
-                e0 = vec_start(q, i);
-#pragma unroll
-            for (int e = 0; e < V; e++) {
-                const bool p = (bits >> e) & 1;
-                const uint32_t slot = q * V + e;
-                const uint32_t d = p ? rp : c + slot - rp;
-                rp += p;
-                if (FAST || (q < nvec && e0 + e >= fp && e0 + e < real_end)) {
-                    const uint64_t vd = ((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1));
-                    store_elem<NTMP, T>(buf[r], e, elem_ptr(vd));
-                }
-            }
-        }
-        return c;
-    }
-};
 
 template <typename T, int NT, int NV, bool FIRST, bool NTMP, bool DB>
 __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
@@ -255,7 +66,7 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
         return;
     }
 
-    const Geo G = plan_geo((uintptr_t)a.base, lo, hi, W, a.log2b, a.s_max);
+    const Geo G = plan_geo(lo, hi, a.log2b, a.s_max);
     Ctx x;
     x.g = G.g;
     x.s = G.s;

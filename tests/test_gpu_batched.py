@@ -1,0 +1,94 @@
+"""GPU parity of the batched partition: every array against the oracle, and
+identical bytes for an array partitioned alone and inside a batch."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_gpu_partition import to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(kind, lengths, seed):
+    n = int(np.sum(lengths))
+    if kind == "u32":
+        data = workloads.keys_u32(n, seed)
+    elif kind == "u64":
+        data = workloads.keys_u64(n, seed)
+    else:
+        data = workloads.records_kv(n, seed)
+    offsets = np.zeros(len(lengths) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(lengths)
+    qs = workloads.uniform_quantiles(len(lengths), seed)
+    pivots = np.zeros(len(lengths), dtype=np.uint64)
+    for k in range(len(lengths)):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        pivots[k] = workloads.pivot_at_quantile_np(data[a:b], qs[k]) if b > a else 0
+    return data, offsets, pivots
+
+
+def _run_batched(ss, data, offsets, pivots, **kw):
+    import torch
+    t = to_device(data)
+    pv = torch.from_numpy(pivots.view(np.int64).copy()).cuda()
+    sp = torch.full((len(pivots),), -7, dtype=torch.int64, device="cuda")
+    st = ss.partition_batched(t, offsets, pv, sp, stats=True, **kw)
+    return to_host(t, data), sp.cpu().numpy().view(np.uint64), st
+
+
+def _check(data, out, offsets, pivots, splits):
+    for k in range(len(pivots)):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        ref = data[a:b].copy()
+        rs = oracle.partition(ref, int(pivots[k]))
+        assert int(splits[k]) == rs, (k, int(splits[k]), rs)
+        gl, gr = oracle.sorted_sides(out[a:b], rs)
+        rl, rr = oracle.sorted_sides(ref, rs)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr), k
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_batched_uneven_lengths(ss, kind):
+    rng = np.random.default_rng(5)
+    lengths = np.concatenate([[0, 1, 2, 63, 64, 65, 0, 4095, 16384, 16385],
+                              workloads.lognormal_lengths(300, 9, median_log2=12.0, sigma_log2=1.5, lo=1, hi=1 << 19),
+                              [1 << 20, (1 << 20) + 3, 7]]).astype(np.int64)
+    data, offsets, pivots = _batch(kind, lengths, 3)
+    out, splits, st = _run_batched(ss, data, offsets, pivots)
+    _check(data, out, offsets, pivots, splits)
+    assert st["levels"] >= 1
+
+
+def test_batched_same_bytes_alone_and_in_mix(ss):
+    lengths = workloads.lognormal_lengths(200, 21, median_log2=13.0)
+    data, offsets, pivots = _batch("u64", lengths, 8)
+    out_mix, splits_mix, _ = _run_batched(ss, data, offsets, pivots)
+    for k in (0, 17, 99, 199):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        alone = data[a:b].copy()
+        out_alone, splits_alone, _ = _run_batched(ss, alone, np.array([0, b - a], dtype=np.uint64), pivots[k:k + 1])
+        assert int(splits_alone[0]) == int(splits_mix[k])
+        assert np.array_equal(out_alone, out_mix[a:b])
+
+
+def test_batched_unaligned_starts_and_tiles(ss):
+    lengths = np.array([5, 100003, 3, 70001, 1, 1 << 18, 33, 9999], dtype=np.int64)
+    data, offsets, pivots = _batch("u64", lengths, 4)
+    for tile in (32768, 65536, 131072):
+        for b in (16, 64):
+            out, splits, _ = _run_batched(ss, data, offsets, pivots, tile_bytes=tile, b=b, engine="regs")
+            _check(data, out, offsets, pivots, splits)
+
+
+def test_batched_config_shape_properties(ss):
+    """The batched benchmark shape (20,000 log-normal arrays around 2^14): every
+    split equals the oracle's count and every array is partitioned."""
+    lengths = workloads.lognormal_lengths(20000, workloads.config_seed(3))
+    data, offsets, pivots = _batch("u64", lengths, workloads.config_seed(3))
+    out, splits, st = _run_batched(ss, data, offsets, pivots)
+    for k in range(0, 20000, 7):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        assert int(splits[k]) == oracle.count_less(data[a:b], int(pivots[k]))
+        assert oracle.is_partitioned(out[a:b], int(pivots[k]), int(splits[k]))
+    assert oracle.fingerprint(out) == oracle.fingerprint(data)
