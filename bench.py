@@ -36,8 +36,8 @@ WORKLOADS = {
     "partition_u64_2p30_q0.01": ("u64", 30, 0.01),
     "partition_u64_2p30_desc": ("u64", 30, "desc"),
 }
-LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_device.h",
-                 "paper_2004_12532_amd/csrc/ss_common.h"]
+LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_levelctx.h",
+                 "paper_2004_12532_amd/csrc/ss_device.h", "paper_2004_12532_amd/csrc/ss_common.h"]
 COUNTER_FILE = os.path.join(ROOT, "profiles", "level0_u64_2p30_counters.json")
 
 
