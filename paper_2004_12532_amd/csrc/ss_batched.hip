@@ -32,20 +32,6 @@
 
 namespace ss {
 
-struct BatchState {
-    uint64_t *start;   // first element of array k
-    uint64_t *len;     // its length
-    const uint64_t *pivot;
-    uint64_t *lo, *hi; // current region (absolute)
-    uint64_t *split;   // absolute split, ~0 while open
-    uint32_t *g;       // groups at the current level (0: finished)
-    uint64_t *first;   // first item of array k at the current level (num + 1 entries)
-    uint32_t *imap;    // item -> array
-    uint64_t *vout;    // item -> splitting position
-    uint64_t *ctl;     // [0] items of the current level, [1] open arrays
-    uint32_t num;
-};
-
 struct BatchGeom {
     char *base;
     uint32_t w, log2b, s_max;

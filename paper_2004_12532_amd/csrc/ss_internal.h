@@ -92,6 +92,25 @@ void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                   uint64_t *d_split, bool sync, RunOut *ro);
 
+// Device state of a batched partition: one entry per array (see ss_batched.hip).
+struct BatchState {
+    uint64_t *start;   // first element of array k (relative to the base)
+    uint64_t *len;     // its length
+    const uint64_t *pivot;
+    uint64_t *lo, *hi; // current region (absolute element indices)
+    uint64_t *split;   // absolute split, ~0 while open
+    uint32_t *g;       // groups at the current level (0: finished)
+    uint64_t *first;   // first item of array k at the current level (num + 1 entries)
+    uint32_t *imap;    // item -> array
+    uint64_t *vout;    // item -> splitting position
+    uint64_t *ctl;     // [0] items of the current level, [1] open arrays
+    uint32_t num;
+};
+int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage);
+uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems);
+int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64_t items_cap, hipStream_t st,
+                 uint64_t *d_splits, bool sync, uint32_t *launches, uint32_t *levels_run);
+
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats);
 size_t lowspace_aux_bytes(size_t n);

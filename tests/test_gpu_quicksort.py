@@ -1,0 +1,82 @@
+"""GPU parity of the quicksort built on the partition against the oracle's sort."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_gpu_partition import gen, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_sorted(ss, a0):
+    t = to_device(a0)
+    st = ss.quicksort(t, stats=True)
+    out = to_host(t, a0)
+    ref = a0.copy()
+    oracle.quicksort(ref)
+    if a0.ndim == 2:
+        assert np.array_equal(out[:, 0], ref[:, 0])          # the key sequence is unique
+        assert oracle.is_sorted(out)
+        # records intact: same multiset of (key, payload)
+        o = out[np.lexsort((out[:, 1], out[:, 0]))]
+        r = ref[np.lexsort((ref[:, 1], ref[:, 0]))]
+        assert np.array_equal(o, r)
+    else:
+        assert np.array_equal(out, ref)
+    return st
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_quicksort_sizes(ss, kind):
+    for n in (0, 1, 2, 3, 17, 1000, 8191, 8192, 8193, 16384, 16385, 40000, 100003, 1 << 20):
+        _check_sorted(ss, gen(kind, n, 40 + n))
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_quicksort_duplicates_and_orders(ss, kind):
+    n = 300001
+    base = gen(kind, n, 12)
+    keys = base[:, 0] if base.ndim == 2 else base
+    top = np.iinfo(keys.dtype).max
+    variants = {
+        "few": keys % 3,
+        "one_value": np.zeros_like(keys) + 5,
+        "max_key": np.full_like(keys, top),
+        "two_values_with_max": np.where(keys % 2 == 0, top, 0).astype(keys.dtype),
+        "ascending": np.sort(keys),
+        "descending": np.sort(keys)[::-1].copy(),
+        "few_distinct_1024": (workloads.keys_few_distinct_u32(n, 3, 1024).astype(keys.dtype)),
+    }
+    for name, k in variants.items():
+        a0 = base.copy()
+        if a0.ndim == 2:
+            a0[:, 0] = k
+        else:
+            a0[:] = k
+        _check_sorted(ss, a0)
+
+
+def test_quicksort_parity_2p26_u32(ss):
+    for a0 in (workloads.keys_u32(1 << 26, workloads.config_seed(2)),
+               workloads.keys_few_distinct_u32(1 << 26, workloads.config_seed(2), 1024)):
+        st = _check_sorted(ss, a0)
+        assert st["levels"] >= 8
+
+
+def test_quicksort_config_2p28_u32_properties(ss):
+    """The sort benchmark shape (2^28 uint32, uniform and 1024 distinct values):
+    sorted and the same multiset as the input."""
+    import torch
+    n = 1 << 28
+    for t in (workloads.keys_u32_torch(n, workloads.config_seed(2), "cuda"),
+              workloads.keys_few_distinct_u32_torch(n, workloads.config_seed(2), "cuda", 1024)):
+        h0 = t.cpu().numpy().view(np.uint32)
+        fp = oracle.fingerprint(h0)
+        del h0
+        ss.quicksort(t)
+        h = t.cpu().numpy().view(np.uint32)
+        assert oracle.is_sorted(h)
+        assert oracle.fingerprint(h) == fp
+        del t, h
+        torch.cuda.empty_cache()
