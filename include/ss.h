@@ -188,6 +188,33 @@ int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, in
                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                          void *stream, ss_stats *stats);
 
+/* Batched partition of disjoint segments of one array: segment k is
+ * d_base[h_starts[k], h_starts[k] + h_lens[k]) in elements (host arrays;
+ * segments may appear in any order but must not overlap), with pivot
+ * d_pivots[k] (device); d_splits[k] (device) receives its split relative to
+ * h_starts[k].  Same algorithm and semantics as ss_partition_batched, which
+ * is the case of back-to-back segments.  Used by the serving loop to put
+ * the pending work of many jobs into one launch sequence. */
+int ss_partition_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
+                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p, void *stream,
+                          ss_stats *stats);
+
+/* The quicksort's median-of-3 pivot of every segment (Section 5.2 quicksort;
+ * the median of the keys at offsets 0, len/2 and len-1): d_pivots[k]
+ * (device) and, if h_pivots != NULL, h_pivots[k] (host, call synchronizes).
+ * Segment lengths must be >= 1. */
+int ss_median3_pivots(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
+                      uint64_t *d_pivots, uint64_t *h_pivots, void *stream);
+
+/* Sort every segment ascending by key in place with the quicksort's
+ * workgroup-local LDS sort (stable radix sort; one workgroup per segment).
+ * Segment lengths must be in [1, ss_sort_segment_cap(dtype)]. */
+int ss_sort_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
+                     void *stream);
+
+/* Largest segment ss_sort_segments accepts: 16384 elements (8192 for SS_KV16). */
+size_t ss_sort_segment_cap(int dtype);
+
 /* Device workspace bytes a call on n elements of dtype with algo uses (the
  * auxiliary memory of the in-place model, Section 2 "Memory Model"). */
 size_t ss_aux_bytes(size_t n, int dtype, int algo);

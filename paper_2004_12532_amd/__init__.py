@@ -71,6 +71,12 @@ _lib.ss_quicksort.argtypes = [_vp, _sz, _int]
 _lib.ss_quicksort_ex.argtypes = [_vp, _sz, _int, ctypes.POINTER(Params), _vp, ctypes.POINTER(Stats)]
 _lib.ss_partition_batched.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp,
                                       ctypes.POINTER(Stats)]
+_lib.ss_partition_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp,
+                                       ctypes.POINTER(Stats)]
+_lib.ss_median3_pivots.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, _vp]
+_lib.ss_sort_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp]
+_lib.ss_sort_segment_cap.argtypes = [_int]
+_lib.ss_sort_segment_cap.restype = _sz
 _lib.ss_aux_bytes.argtypes = [_sz, _int, _int]
 _lib.ss_aux_bytes.restype = _sz
 _lib.ss_strerror.argtypes = [_int]
@@ -80,7 +86,8 @@ _lib.ss_last_error.restype = ctypes.c_char_p
 _lib.ss_probe_bandwidth.argtypes = [_vp, _sz, _int, _vp, ctypes.POINTER(ctypes.c_float)]
 _lib.ss_device_info.argtypes = [ctypes.POINTER(_int)] * 4
 for _f in ("ss_partition", "ss_partition_ex", "ss_quicksort", "ss_quicksort_ex", "ss_partition_batched",
-           "ss_probe_bandwidth", "ss_device_info"):
+           "ss_probe_bandwidth", "ss_device_info", "ss_partition_segments", "ss_median3_pivots",
+           "ss_sort_segments"):
     getattr(_lib, _f).restype = _int
 
 LIB_PATH = _SO
@@ -191,6 +198,52 @@ def partition_batched(base, offsets, pivots, splits, *, stats: bool = False, str
                                      ctypes.byref(p), _stream(stream), ctypes.byref(st) if stats else None),
            "ss_partition_batched")
     return st.as_dict() if stats else None
+
+
+def _u64_host(x):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def partition_segments(base, starts, lens, pivots, splits, *, stats: bool = False, stream=None, **kw):
+    """Partition disjoint segments base[starts[k]:starts[k]+lens[k]] by pivots[k] (int64 CUDA
+    tensor); splits (int64 CUDA tensor) receives each segment's split."""
+    ptr, _, dt = _array(base)
+    s_arr, s_ptr = _u64_host(starts)
+    l_arr, l_ptr = _u64_host(lens)
+    p = make_params(**kw)
+    st = Stats()
+    _check(_lib.ss_partition_segments(ptr, s_ptr, l_ptr, len(s_arr), dt, ctypes.c_void_p(pivots.data_ptr()),
+                                      ctypes.c_void_p(splits.data_ptr()), ctypes.byref(p), _stream(stream),
+                                      ctypes.byref(st) if stats else None), "ss_partition_segments")
+    return st.as_dict() if stats else None
+
+
+def median3_pivots(base, starts, lens, d_pivots, *, host=True, stream=None):
+    """Median-of-3 pivot of every segment into d_pivots (int64 CUDA tensor); returns them
+    as a numpy uint64 array when host is true."""
+    import numpy as np
+    ptr, _, dt = _array(base)
+    s_arr, s_ptr = _u64_host(starts)
+    l_arr, l_ptr = _u64_host(lens)
+    out = np.zeros(len(s_arr), dtype=np.uint64) if host else None
+    _check(_lib.ss_median3_pivots(ptr, s_ptr, l_ptr, len(s_arr), dt, ctypes.c_void_p(d_pivots.data_ptr()),
+                                  ctypes.c_void_p(out.ctypes.data) if host else None, _stream(stream)),
+           "ss_median3_pivots")
+    return out
+
+
+def sort_segments(base, starts, lens, *, stream=None):
+    """Sort every segment (length <= sort_segment_cap) in place with the LDS sort."""
+    ptr, _, dt = _array(base)
+    s_arr, s_ptr = _u64_host(starts)
+    l_arr, l_ptr = _u64_host(lens)
+    _check(_lib.ss_sort_segments(ptr, s_ptr, l_ptr, len(s_arr), dt, _stream(stream)), "ss_sort_segments")
+
+
+def sort_segment_cap(dtype: int) -> int:
+    return _lib.ss_sort_segment_cap(dtype)
 
 
 def aux_bytes(n: int, dtype: int, algo="smoothed") -> int:

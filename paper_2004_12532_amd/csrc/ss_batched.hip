@@ -25,6 +25,7 @@
 #include "ss_internal.h"
 #include "ss_levelctx.h"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -401,34 +402,17 @@ uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_ele
     return cap;
 }
 
-}  // namespace ss
-
-using namespace ss;
-
-extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, int dtype,
-                                    const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
-                                    void *stream, ss_stats *stats)
+// Batched partition of segments [starts[k], starts[k] + lens[k]) of d_base
+// given on the host; shared by both batched entry points.
+static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t *lens, size_t num, int dtype,
+                            const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p, void *stream,
+                            ss_stats *stats)
 {
-    const int w = elem_size(dtype);
-    if (!w)
-        return fail_msg(SS_EINVAL, "unknown dtype");
-    if (num == 0)
-        return SS_OK;
-    if (!h_offsets || !d_pivots || !d_splits)
-        return fail_msg(SS_EINVAL, "null offsets, pivots or splits");
-    if (num > (1u << 30))
-        return fail_msg(SS_EINVAL, "too many arrays");
-    for (size_t k = 0; k < num; k++)
-        if (h_offsets[k + 1] < h_offsets[k])
-            return fail_msg(SS_EINVAL, "offsets must be non-decreasing");
-    const uint64_t total = h_offsets[num];
-    int rc = check_array(d_base, (size_t)total, dtype);
-    if (rc)
-        return rc;
     if (((uintptr_t)d_splits % 8) || ((uintptr_t)d_pivots % 8))
         return fail_msg(SS_EINVAL, "pivots and splits must be 8-byte aligned");
     Resolved R;
-    if ((rc = resolve_params(p, dtype, &R)))
+    int rc = resolve_params(p, dtype, &R);
+    if (rc)
         return rc;
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
@@ -441,10 +425,7 @@ extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, siz
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
         return fail_device(e, "hipGetDevice");
-    std::vector<uint64_t> lens(num);
-    for (size_t k = 0; k < num; k++)
-        lens[k] = h_offsets[k + 1] - h_offsets[k];
-    const uint64_t items_cap = batched_items_cap(lens.data(), (uint32_t)num, R.tile / R.w);
+    const uint64_t items_cap = batched_items_cap(lens, (uint32_t)num, R.tile / R.w);
     BatchState B;
     uint64_t *stage = nullptr;
     if ((rc = batched_state(dev, stream, (uint32_t)num, items_cap, &B, &stage)))
@@ -453,8 +434,8 @@ extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, siz
     // the previous call on this stream may still read the staging buffer
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return fail_device(e, "hipStreamSynchronize");
-    std::memcpy(stage, h_offsets, num * sizeof(uint64_t));
-    std::memcpy(stage + num, lens.data(), num * sizeof(uint64_t));
+    std::memcpy(stage, starts, num * sizeof(uint64_t));
+    std::memcpy(stage + num, lens, num * sizeof(uint64_t));
     if ((e = hipMemcpyAsync(B.start, stage, 2 * num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess)
         return fail_device(e, "hipMemcpyAsync");
     RunOut ro;
@@ -484,14 +465,73 @@ extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, siz
     if (stats) {
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return fail_device(e, "hipStreamSynchronize");
-        ro.levels_run = 0;
         fill_stats(stats, ro, R, dtype);
         stats->levels = levels_run;
-        stats->aux_bytes = 0;
-        {
-            std::lock_guard<std::mutex> lk(g_b_mu);
-            stats->aux_bytes = g_b[std::make_pair(dev, stream)].dev_bytes;
-        }
+        std::lock_guard<std::mutex> lk(g_b_mu);
+        stats->aux_bytes = g_b[std::make_pair(dev, stream)].dev_bytes;
     }
     return SS_OK;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, int dtype,
+                                    const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
+                                    void *stream, ss_stats *stats)
+{
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    if (num == 0)
+        return SS_OK;
+    if (!h_offsets || !d_pivots || !d_splits)
+        return fail_msg(SS_EINVAL, "null offsets, pivots or splits");
+    if (num > (1u << 30))
+        return fail_msg(SS_EINVAL, "too many arrays");
+    for (size_t k = 0; k < num; k++)
+        if (h_offsets[k + 1] < h_offsets[k])
+            return fail_msg(SS_EINVAL, "offsets must be non-decreasing");
+    int rc = check_array(d_base, (size_t)h_offsets[num], dtype);
+    if (rc)
+        return rc;
+    std::vector<uint64_t> lens(num);
+    for (size_t k = 0; k < num; k++)
+        lens[k] = h_offsets[k + 1] - h_offsets[k];
+    return batched_segments(d_base, h_offsets, lens.data(), num, dtype, d_pivots, d_splits, p, stream, stats);
+}
+
+extern "C" int ss_partition_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num,
+                                     int dtype, const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
+                                     void *stream, ss_stats *stats)
+{
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    if (num == 0)
+        return SS_OK;
+    if (!h_starts || !h_lens || !d_pivots || !d_splits)
+        return fail_msg(SS_EINVAL, "null starts, lengths, pivots or splits");
+    if (num > (1u << 30))
+        return fail_msg(SS_EINVAL, "too many segments");
+    uint64_t end = 0;
+    {
+        // segments must be disjoint: check on a sorted copy of (start, end)
+        std::vector<std::pair<uint64_t, uint64_t>> iv(num);
+        for (size_t k = 0; k < num; k++) {
+            if (h_starts[k] + h_lens[k] < h_starts[k])
+                return fail_msg(SS_EINVAL, "segment overflows");
+            iv[k] = std::make_pair(h_starts[k], h_starts[k] + h_lens[k]);
+            end = iv[k].second > end ? iv[k].second : end;
+        }
+        std::sort(iv.begin(), iv.end());
+        for (size_t k = 1; k < num; k++)
+            if (iv[k].first < iv[k - 1].second && iv[k].second > iv[k].first && iv[k - 1].second > iv[k - 1].first)
+                return fail_msg(SS_EINVAL, "segments overlap");
+    }
+    int rc = check_array(d_base, (size_t)end, dtype);
+    if (rc)
+        return rc;
+    return batched_segments(d_base, h_starts, h_lens, num, dtype, d_pivots, d_splits, p, stream, stats);
 }

@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(256) k_qpivot(const char *base, const uint64_t
         b = c;
     const uint64_t p = a > b ? a : b;  // median of the three
     piv_dev[k] = p;
-    piv_host[k] = p;
+    if (piv_host)
+        piv_host[k] = p;
 }
 
 template <typename T>
@@ -459,4 +460,116 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
 extern "C" int ss_quicksort(void *d_ptr, size_t n, int dtype)
 {
     return ss_quicksort_ex(d_ptr, n, dtype, nullptr, nullptr, nullptr);
+}
+
+namespace ss {
+
+// Upload num (start, len) pairs through the quicksort staging buffer into the
+// device list area; returns device pointers to the starts and lengths.
+static int upload_segments(int dev, hipStream_t st, const uint64_t *h_starts, const uint64_t *h_lens, size_t num,
+                           QsWork **wout, uint64_t **d_starts, uint64_t **d_lens)
+{
+    QsWork *w = nullptr;
+    int rc = qs_reserve(dev, st, 2 * num + 16, 16, 2 * num + 16, &w);
+    if (rc)
+        return rc;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)  // the staging buffer may still be read
+        return fail_device(e, "hipStreamSynchronize");
+    std::memcpy(w->stage, h_starts, num * sizeof(uint64_t));
+    std::memcpy(w->stage + num, h_lens, num * sizeof(uint64_t));
+    if ((e = hipMemcpyAsync(w->dev, w->stage, 2 * num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return fail_device(e, "hipMemcpyAsync");
+    *wout = w;
+    *d_starts = w->dev;
+    *d_lens = w->dev + num;
+    return SS_OK;
+}
+
+static int check_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
+                          uint64_t max_len)
+{
+    if (!elem_size(dtype))
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    if (num && (!h_starts || !h_lens))
+        return fail_msg(SS_EINVAL, "null starts or lengths");
+    uint64_t end = 0;
+    for (size_t k = 0; k < num; k++) {
+        if (h_lens[k] == 0 || h_lens[k] > max_len)
+            return fail_msg(SS_EINVAL, "segment length out of range");
+        if (h_starts[k] + h_lens[k] > end)
+            end = h_starts[k] + h_lens[k];
+    }
+    return check_array(d_base, (size_t)end, dtype);
+}
+
+}  // namespace ss
+
+extern "C" size_t ss_sort_segment_cap(int dtype)
+{
+    return elem_size(dtype) ? (size_t)quicksort_leaf_cap(dtype) : 0;
+}
+
+extern "C" int ss_median3_pivots(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num,
+                                 int dtype, uint64_t *d_pivots, uint64_t *h_pivots, void *stream)
+{
+    int rc = check_segments(d_base, h_starts, h_lens, num, dtype, ~0ull);
+    if (rc)
+        return rc;
+    if (num == 0)
+        return SS_OK;
+    if (!d_pivots || ((uintptr_t)d_pivots % 8))
+        return fail_msg(SS_EINVAL, "d_pivots must be an 8-byte aligned device array");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    QsWork *w = nullptr;
+    uint64_t *ds = nullptr, *dl = nullptr;
+    if ((rc = upload_segments(dev, st, h_starts, h_lens, num, &w, &ds, &dl)))
+        return rc;
+    BatchState B;
+    std::memset(&B, 0, sizeof(B));
+    B.start = ds;
+    B.len = dl;
+    switch (dtype) {
+    case SS_U32: e = launch_qpivot<uint32_t>((const char *)d_base, B, (uint32_t)num, d_pivots, nullptr, st); break;
+    case SS_U64: e = launch_qpivot<uint64_t>((const char *)d_base, B, (uint32_t)num, d_pivots, nullptr, st); break;
+    default: e = launch_qpivot<KV>((const char *)d_base, B, (uint32_t)num, d_pivots, nullptr, st); break;
+    }
+    if (e != hipSuccess)
+        return fail_device(e, "pivot launch");
+    if (h_pivots) {
+        if ((e = hipMemcpyAsync(h_pivots, d_pivots, num * sizeof(uint64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return fail_device(e, "hipMemcpyAsync");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return fail_device(e, "hipStreamSynchronize");
+    }
+    return SS_OK;
+}
+
+extern "C" int ss_sort_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num,
+                                int dtype, void *stream)
+{
+    int rc = check_segments(d_base, h_starts, h_lens, num, dtype, elem_size(dtype) ? quicksort_leaf_cap(dtype) : 0);
+    if (rc)
+        return rc;
+    if (num == 0)
+        return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    QsWork *w = nullptr;
+    uint64_t *ds = nullptr, *dl = nullptr;
+    if ((rc = upload_segments(dev, st, h_starts, h_lens, num, &w, &ds, &dl)))
+        return rc;
+    for (size_t k0 = 0; k0 < num; k0 += 65535) {
+        const uint32_t cnt = (uint32_t)(num - k0 < 65535 ? num - k0 : 65535);
+        if ((e = launch_qleaf(dtype, (char *)d_base, ds + k0, dl + k0, cnt, st)) != hipSuccess)
+            return fail_device(e, "segment sort launch");
+    }
+    return SS_OK;
 }

@@ -92,3 +92,46 @@ def test_batched_config_shape_properties(ss):
         assert int(splits[k]) == oracle.count_less(data[a:b], int(pivots[k]))
         assert oracle.is_partitioned(out[a:b], int(pivots[k]), int(splits[k]))
     assert oracle.fingerprint(out) == oracle.fingerprint(data)
+
+
+def test_segments_any_order_with_gaps(ss):
+    import torch
+    rng = np.random.default_rng(2)
+    n = 400000
+    data = workloads.keys_u64(n, 77)
+    # disjoint segments with gaps, given out of order
+    cuts = np.sort(rng.choice(np.arange(1, n), size=120, replace=False))
+    bounds = np.concatenate([[0], cuts, [n]])
+    segs = [(int(bounds[i]) + 3, int(bounds[i + 1] - bounds[i]) - 3) for i in range(len(bounds) - 1)
+            if bounds[i + 1] - bounds[i] > 3]
+    order = rng.permutation(len(segs))
+    starts = np.array([segs[i][0] for i in order], dtype=np.uint64)
+    lens = np.array([segs[i][1] for i in order], dtype=np.uint64)
+    pivots = np.array([workloads.pivot_at_quantile_np(data[s:s + l], 0.3) for s, l in zip(starts, lens)],
+                      dtype=np.uint64)
+    t = to_device(data)
+    pv = torch.from_numpy(pivots.view(np.int64).copy()).cuda()
+    sp = torch.empty(len(starts), dtype=torch.int64, device="cuda")
+    ss.partition_segments(t, starts, lens, pv, sp)
+    out = to_host(t, data)
+    splits = sp.cpu().numpy().view(np.uint64)
+    covered = np.zeros(n, dtype=bool)
+    for k, (s, l) in enumerate(zip(starts, lens)):
+        s, l = int(s), int(l)
+        covered[s:s + l] = True
+        ref = data[s:s + l].copy()
+        rs = oracle.partition(ref, int(pivots[k]))
+        assert int(splits[k]) == rs
+        gl, gr = oracle.sorted_sides(out[s:s + l], rs)
+        rl, rr = oracle.sorted_sides(ref, rs)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+    assert np.array_equal(out[~covered], data[~covered])   # the gaps are untouched
+
+
+def test_segments_reject_overlap(ss):
+    import torch
+    t = to_device(workloads.keys_u64(1000, 1))
+    pv = torch.zeros(2, dtype=torch.int64, device="cuda")
+    sp = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with pytest.raises(ss.SSError):
+        ss.partition_segments(t, [0, 50], [100, 100], pv, sp)

@@ -80,3 +80,40 @@ def test_quicksort_config_2p28_u32_properties(ss):
         assert oracle.fingerprint(h) == fp
         del t, h
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_sort_segments_and_median3(ss, kind):
+    import torch
+    rng = np.random.default_rng(4)
+    cap = ss.sort_segment_cap({"u32": ss.SS_U32, "u64": ss.SS_U64, "kv": ss.SS_KV16}[kind])
+    n = 600000
+    data = gen(kind, n, 91)
+    lens = rng.integers(1, cap + 1, size=40)
+    starts = np.cumsum(np.concatenate([[5], lens[:-1] + rng.integers(0, 50, size=39)])).astype(np.uint64)
+    assert int(starts[-1] + lens[-1]) <= n
+    t = to_device(data)
+    keys = data[:, 0] if data.ndim == 2 else data
+    d_piv = torch.empty(len(lens), dtype=torch.int64, device="cuda")
+    hp = ss.median3_pivots(t, starts, lens, d_piv)
+    for k, (s, l) in enumerate(zip(starts, lens)):
+        s, l = int(s), int(l)
+        trio = sorted([int(keys[s]), int(keys[s + l // 2]), int(keys[s + l - 1])])
+        assert int(hp[k]) == trio[1]
+    assert np.array_equal(d_piv.cpu().numpy().view(np.uint64), hp)
+    ss.sort_segments(t, starts, lens)
+    out = to_host(t, data)
+    for s, l in zip(starts, lens):
+        s, l = int(s), int(l)
+        ref = data[s:s + l].copy()
+        oracle.quicksort(ref)
+        seg = out[s:s + l]
+        if data.ndim == 2:
+            assert np.array_equal(seg[:, 0], ref[:, 0])
+            # the LDS sort is stable: equal keys keep their input order
+            order = np.argsort(data[s:s + l, 0], kind="stable")
+            assert np.array_equal(seg, data[s:s + l][order])
+        else:
+            assert np.array_equal(seg, ref)
+    with pytest.raises(ss.SSError):
+        ss.sort_segments(t, [0], [cap + 1])

@@ -1,0 +1,71 @@
+"""GPU: the serving loop's results against the oracle, and the same bytes for a
+job served alone and inside a mix of concurrently admitted jobs."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _server(ss, budget=4 << 30):
+    from paper_2004_12532_amd.serving import Server
+    return Server(budget_bytes=budget, keep_outputs=True)
+
+
+def _input_of(job):
+    import workloads
+    a = np.empty((job.n, 2), dtype=np.uint64)
+    a[:, 0] = workloads.splitmix64_np(job.seed, 0, job.n)
+    a[:, 1] = np.arange(job.n, dtype=np.uint64) + np.uint64(job.job_id << 32)
+    return a
+
+
+def _check_job(job, out):
+    a0 = _input_of(job)
+    if job.kind == "partition":
+        ref = a0.copy()
+        rs = oracle.partition(ref, job.pivot)
+        assert job.split == rs
+        gl, gr = oracle.sorted_sides(out, rs)
+        rl, rr = oracle.sorted_sides(ref, rs)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+    else:
+        ref = a0.copy()
+        oracle.quicksort(ref)
+        assert np.array_equal(out[:, 0], ref[:, 0])
+        o = out[np.lexsort((out[:, 1], out[:, 0]))]
+        r = ref[np.lexsort((ref[:, 1], ref[:, 0]))]
+        assert np.array_equal(o, r)
+
+
+def test_serving_results_and_alone_vs_mix(ss):
+    from paper_2004_12532_amd.serving import make_jobs, latency_summary
+    jobs = make_jobs(48, 0.0, 5, lo_log2=10.0, hi_log2=19.0)   # all available at once: one big mix
+    srv = _server(ss)
+    srv.run(jobs, realtime=False)
+    assert srv.max_batch >= 20                                  # many jobs shared the launches
+    for job in jobs:
+        _check_job(job, srv.outputs[job.job_id])
+    # the same jobs one at a time
+    for job in jobs[::5]:
+        from paper_2004_12532_amd.serving import Job
+        solo = Job(job_id=job.job_id, kind=job.kind, n=job.n, seed=job.seed, arrival=0.0,
+                   quantile=job.quantile, pivot=job.pivot)
+        s2 = _server(ss, budget=1 << 30)
+        s2.run([solo], realtime=False)
+        assert np.array_equal(s2.outputs[job.job_id], srv.outputs[job.job_id]), job.job_id
+        assert solo.split == job.split
+    summ = latency_summary(jobs)
+    assert summ["jobs"] == 48 and summ["p99_ms"] >= summ["p50_ms"]
+
+
+def test_serving_realtime_arrivals_and_budget(ss):
+    from paper_2004_12532_amd.serving import make_jobs
+    jobs = make_jobs(30, 400.0, 9, lo_log2=12.0, hi_log2=20.0)
+    srv = _server(ss, budget=64 << 20)   # 64 MiB: forces jobs to wait for memory
+    srv.run(jobs, realtime=True)
+    for job in jobs:
+        assert job.done >= job.admitted >= job.arrival
+        _check_job(job, srv.outputs[job.job_id])
+    assert srv.arena.used == 0
