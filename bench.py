@@ -88,34 +88,25 @@ def cpu_baseline(seconds_budget: float = 12.0):
                       "median, %d runs, median time %.3f s, 1 thread" % (len(times), t)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="partition_u64_2p30_q0.5", choices=sorted(WORKLOADS))
-    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace"])
-    ap.add_argument("--b", type=int, default=0)
-    ap.add_argument("--tile-bytes", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-probe", action="store_true")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+def _exit_multi_gpu(gpus):
+    if gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
-    if not 1 <= args.steps <= 24:
-        print("bench.py: --steps must be in [1, 24] (one 8 GiB input copy per timed step)", file=sys.stderr)
-        sys.exit(2)
 
+
+def _u64_tensor_scalar(torch, v, dev):
+    return torch.tensor([v - (1 << 64) if v >> 63 else v], dtype=torch.int64, device=dev)
+
+
+def run_partition(args, workload, algo="smoothed"):
+    """The headline: K partitions of fresh resident copies of 2^30 uint64 keys."""
     import torch
 
     import paper_2004_12532_amd as ss
     import workloads
 
-    torch.cuda.set_device(0)
-    dtype, log2n, q = WORKLOADS[args.workload]
+    dtype, log2n, q = WORKLOADS[workload]
     n = 1 << log2n
     w = 8
     dev = torch.device("cuda", 0)
@@ -124,10 +115,10 @@ def main():
     pivot = workloads.pivot_at_quantile_torch(pristine, 0.5 if q == "desc" else q)
     if q == "desc":
         pristine = workloads.sort_descending_u64_torch(pristine)
-    expected = int((workloads.to_unsigned_order(pristine) < workloads.to_unsigned_order(
-        torch.tensor([pivot - (1 << 64) if pivot >> 63 else pivot], dtype=torch.int64, device=dev))).sum().item())
+    expected = int((workloads.to_unsigned_order(pristine) <
+                    workloads.to_unsigned_order(_u64_tensor_scalar(torch, pivot, dev))).sum().item())
     bufs = [torch.empty_like(pristine) for _ in range(args.steps)]
-    kw = dict(algo=args.algo, b=args.b, tile_bytes=args.tile_bytes)
+    kw = dict(algo=algo, b=args.b, tile_bytes=args.tile_bytes)
 
     def restore(k):
         bufs[k].copy_(pristine)
@@ -165,7 +156,8 @@ def main():
     del bufs
     torch.cuda.empty_cache()
 
-    traffic = counter_traffic(alg_bytes)
+    traffic = counter_traffic(alg_bytes) if (algo == "smoothed" and workload == "partition_u64_2p30_q0.5"
+                                              and not args.b and not args.tile_bytes) else None
     out = {
         "metric": "partition GB/s & % HBM peak, 2^30 u64; batched vs per-array launch; p99 latency",
         "value": round(value, 2),
@@ -180,10 +172,10 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": args.workload,
+            "workload": workload,
             "n": n,
             "pivot_quantile": q,
-            "algo": args.algo,
+            "algo": algo,
             "b": stats["b"],
             "s_max": stats["s_max"],
             "grid": stats["grid"],
@@ -204,16 +196,218 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
+            "kernel": {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
+                       "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
+                       "lowspace": "whole Low-Space call (all its kernels)"}[algo],
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "probe": probe,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
     if not ok:
-        print("bench.py: split mismatch %s vs expected %d" % (splits, expected), file=sys.stderr)
+        out["error"] = "split mismatch %s vs expected %d" % (splits, expected)
+    return out
+
+
+def run_quicksort(args, distinct):
+    """K quicksorts of fresh copies of 2^28 uint32 keys (uniform, or 1024 distinct values)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2004_12532_amd as ss
+    import workloads
+
+    n = 1 << 28
+    dev = torch.device("cuda", 0)
+    seed = workloads.config_seed(2)
+    pristine = (workloads.keys_few_distinct_u32_torch(n, seed, dev, distinct) if distinct
+                else workloads.keys_u32_torch(n, seed, dev))
+    steps = min(args.steps, 8)
+    bufs = [pristine.clone() for _ in range(steps)]
+    ss.quicksort(pristine.clone())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        stats.append(ss.quicksort(bufs[k], stats=True, time=True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ok = bool((bufs[0][1:].to(torch.int64) & 0xFFFFFFFF >= bufs[0][:-1].to(torch.int64) & 0xFFFFFFFF).all())
+    # CPU oracle sort on a 2^24 sample of the same generator
+    m = 1 << 24
+    a = workloads.keys_few_distinct_u32(m, seed, distinct) if distinct else workloads.keys_u32(m, seed)
+    t1 = time.perf_counter()
+    oracle.quicksort(a)
+    tc = time.perf_counter() - t1
+    return {"metric": "quicksort elements/s, 2^28 uint32" + (" (%d distinct values)" % distinct if distinct else ""),
+            "value": round(n * steps / wall, 1), "unit": "elements/s", "ms_per_sort": round(wall / steps * 1e3, 3),
+            "device_ms": round(sum(x["total_ms"] for x in stats) / steps, 3),
+            "partition_levels": stats[0]["levels"], "sorted": ok,
+            "effective_GBps_per_level": round(2 * n * 4 * stats[0]["levels"] / (wall / steps) / 1e9, 1),
+            "config": {"workload": "quicksort_u32_2p28" + ("_d%d" % distinct if distinct else ""), "n": n,
+                       "leaf": 1 << 14, "pivot": "median of 3"},
+            "cpu_baseline": {"value": round(m / tc, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
+                             "sample": "serial quicksort of 2^24 keys of the same generator, %.3f s" % tc}}
+
+
+def run_batched(args):
+    """20,000 uint64 arrays, log-normal lengths around 2^14: one batched call vs one call per array."""
+    import numpy as np
+    import torch
+
+    import paper_2004_12532_amd as ss
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    seed = workloads.config_seed(3)
+    lens = workloads.lognormal_lengths(20000, seed)
+    offs = np.zeros(len(lens) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(lens)
+    total = int(offs[-1])
+    pristine = workloads.keys_u64_torch(total, seed, dev)
+    qs = workloads.uniform_quantiles(len(lens), seed)
+    piv = np.array([min((1 << 64) - 1, int(q * (1 << 64))) for q in qs], dtype=np.uint64)
+    d_piv = torch.from_numpy(piv.view(np.int64).copy()).to(dev)
+    d_split = torch.empty(len(lens), dtype=torch.int64, device=dev)
+    buf = torch.empty_like(pristine)
+    reps = max(1, min(args.steps, 5))
+    # batched: one call over all arrays
+    bt = []
+    for r in range(reps + 1):
+        buf.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ss.partition_batched(buf, offs, d_piv, d_split)
+        torch.cuda.synchronize()
+        if r:
+            bt.append(time.perf_counter() - t0)
+    splits_b = d_split.cpu().numpy().copy()
+    # per-array: one asynchronous call per array on one stream, an event after each
+    st = torch.cuda.current_stream()
+    pt, lat = [], None
+    for r in range(2):
+        buf.copy_(pristine)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(lens))]
+        t0 = time.perf_counter()
+        ev0.record(st)
+        for k in range(len(lens)):
+            a, b = int(offs[k]), int(offs[k + 1])
+            ss.partition_async(buf[a:b], int(piv[k]), d_split[k:k + 1])
+            evs[k].record(st)
+        torch.cuda.synchronize()
+        pt.append(time.perf_counter() - t0)
+        lat = np.array([ev0.elapsed_time(e) for e in evs])
+    splits_p = d_split.cpu().numpy()
+    bytes_ = 2 * 8 * total
+    tb = min(bt)
+    tp = min(pt)
+    return {"metric": "batched partition GB/s and p99 latency, 20000 uint64 arrays (log-normal, median 2^14)",
+            "value": round(bytes_ / tb / 1e9, 1), "unit": "GB/s",
+            "batched": {"ms": round(tb * 1e3, 3), "GBps": round(bytes_ / tb / 1e9, 1),
+                        "elements_per_s": round(total / tb, 1), "p50_ms": round(tb * 1e3, 3),
+                        "p99_ms": round(tb * 1e3, 3)},
+            "per_array": {"ms": round(tp * 1e3, 3), "GBps": round(bytes_ / tp / 1e9, 1),
+                          "elements_per_s": round(total / tp, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat, 99)), 3)},
+            "speedup": round(tp / tb, 2), "splits_agree": bool(np.array_equal(splits_b, splits_p)),
+            "config": {"workload": "batched_u64_20000", "arrays": len(lens), "elements": total,
+                       "pivot": "u-quantile of the key distribution, u ~ U[0.05, 0.95]"}}
+
+
+def run_serving(args):
+    """KV16 jobs (70% partition, 30% sort), log-uniform lengths 2^10..2^26, 64 GiB budget."""
+    import torch
+
+    from paper_2004_12532_amd.serving import Server, latency_summary, make_jobs
+
+    njobs = args.serving_jobs
+    srv = Server(budget_bytes=64 << 30)
+    warm = make_jobs(8, 0.0, 11, lo_log2=10, hi_log2=16)
+    srv.run(warm, realtime=False)
+    cap_jobs = make_jobs(njobs, 0.0, 12)
+    srv.run(cap_jobs, realtime=False)
+    cap = latency_summary(cap_jobs)
+    C = cap["jobs_per_s"]
+    print("serving: capacity %.2f jobs/s" % C, file=sys.stderr, flush=True)
+    loads = {}
+    for frac in (0.5, 0.8, 0.95):
+        jobs = make_jobs(njobs, frac * C, 13 + int(frac * 100))
+        srv.run(jobs, realtime=True)
+        loads["%.2f" % frac] = latency_summary(jobs)
+        print("serving: load %.2f done: %s" % (frac, loads["%.2f" % frac]), file=sys.stderr, flush=True)
+    return {"metric": "serving p50/p99 latency and records/s (KV16 partition and sort jobs)",
+            "value": loads["0.80"]["p99_ms"], "unit": "ms (p99 at 80% load)", "higher_is_better": False,
+            "capacity": cap, "loads": loads, "ticks": srv.ticks, "max_jobs_per_tick": srv.max_batch,
+            "config": {"workload": "serving_kv16", "jobs_per_load": njobs, "budget_GiB": 64,
+                       "mix": "70% partition, 30% quicksort", "lengths": "log-uniform 2^10..2^26"}}
+
+
+SUITE = ["partition_u64_2p30_q0.1", "partition_u64_2p30_q0.01", "partition_u64_2p30_desc",
+         "partition_u64_2p30_q0.5:strided", "partition_u64_2p30_q0.5:lowspace",
+         "quicksort_u32_2p28", "quicksort_u32_2p28_d1024", "batched_u64_20000", "serving_kv16"]
+
+
+def run_named(args, name):
+    if name.startswith("partition_"):
+        wl, _, algo = name.partition(":")
+        return run_partition(args, wl, algo or args.algo)
+    if name == "quicksort_u32_2p28":
+        return run_quicksort(args, None)
+    if name == "quicksort_u32_2p28_d1024":
+        return run_quicksort(args, 1024)
+    if name == "batched_u64_20000":
+        return run_batched(args)
+    if name == "serving_kv16":
+        return run_serving(args)
+    raise SystemExit("unknown workload " + name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="partition_u64_2p30_q0.5",
+                    choices=sorted(WORKLOADS) + ["quicksort_u32_2p28", "quicksort_u32_2p28_d1024",
+                                                 "batched_u64_20000", "serving_kv16"])
+    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace"])
+    ap.add_argument("--b", type=int, default=0)
+    ap.add_argument("--tile-bytes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=120)
+    ap.add_argument("--suite", default="", help="also run the other workloads, writing their lines to this file")
+    args = ap.parse_args()
+    _exit_multi_gpu(args.gpus)
+    if not 1 <= args.steps <= 24:
+        print("bench.py: --steps must be in [1, 24] (one input copy per timed step)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    out = run_named(args, args.workload)
+    print(json.dumps(out), flush=True)
+    if args.suite:
+        sub = argparse.Namespace(**vars(args))
+        sub.no_cpu_baseline = True
+        sub.no_probe = True
+        sub.steps = min(args.steps, 5)
+        sub.warmup = 1
+        with open(args.suite, "w") as f:
+            for name in SUITE:
+                t0 = time.perf_counter()
+                res = run_named(sub, name)
+                res["bench_wall_s"] = round(time.perf_counter() - t0, 1)
+                f.write(json.dumps(res) + "\n")
+                f.flush()
+                print("suite: %s done in %.1f s" % (name, res["bench_wall_s"]), file=sys.stderr, flush=True)
+                torch.cuda.empty_cache()
+    if out.get("error"):
+        print("bench.py: " + out["error"], file=sys.stderr)
         sys.exit(1)
 
 

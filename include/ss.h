@@ -71,7 +71,8 @@ enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2 };
 
 enum ss_status {
     SS_OK = 0,
-    SS_EINVAL = -1,        /* bad argument: null pointer with n > 0, misaligned pointer, bad enum or parameter */
+    SS_EINVAL = -1,        /* bad argument: null pointer with n > 0, misaligned pointer, bad enum or parameter,
+                              n above 2^40, or an array of 2^32 lines or more (line indices are 32-bit) */
     SS_ENOMEM = -2,        /* device workspace allocation failed */
     SS_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
     SS_EUNSUPPORTED = -4,  /* valid but unsupported combination (e.g. an algorithm not offered for a dtype) */

@@ -234,6 +234,14 @@ int check_array(const void *d_ptr, size_t n, int dtype)
     return SS_OK;
 }
 
+// Line indices are 32-bit: the first level's line count must fit.
+int check_lines(uint64_t n, const Resolved &R)
+{
+    if ((n + 2ull * R.b) / R.b >= (1ull << 32))
+        return fail_msg(SS_EINVAL, "array has 2^32 lines or more for this b; use longer lines");
+    return SS_OK;
+}
+
 // Run the recursion of Smoothed Striding (or the single Strided step) on
 // [lo0, hi0) of the array.  Writes the result record to ws->result and the
 // split to d_split.  When `sync` the host finishes the recursion if the
@@ -438,6 +446,8 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
     if (R.algo == SS_LOWSPACE)
         return lowspace_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split,
                                   stats);
+    if ((rc = check_lines(n, R)))
+        return rc;
     if (d_split && ((uintptr_t)d_split % 8))
         return fail_msg(SS_EINVAL, "d_split not 8-byte aligned");
     const bool sync = h_split || stats;

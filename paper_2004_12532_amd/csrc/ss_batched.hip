@@ -420,6 +420,9 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses the register engine");
     if (!p || !p->max_levels)
         R.levels = 6;
+    for (size_t k = 0; k < num; k++)
+        if ((rc = check_lines(lens[k], R)))
+            return rc;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int dev = 0;

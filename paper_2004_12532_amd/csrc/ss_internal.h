@@ -85,6 +85,7 @@ int fail_msg(int code, const std::string &msg);
 int elem_size(int dtype);
 int check_array(const void *d_ptr, size_t n, int dtype);
 int resolve_params(const ss_params *p, int dtype, Resolved *r);
+int check_lines(uint64_t n, const Resolved &R);
 int device_info(int dev, int *cus, int *lds);
 int occupancy(int dev, const void *fn, int nt, int *blocks);
 int get_workspace(int dev, void *stream, Workspace **out);

@@ -426,6 +426,8 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the register engine");
     if (!p || !p->max_levels)
         R.levels = 6;
+    if ((rc = check_lines(n, R)))
+        return rc;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     const bool timing = (R.flags & SS_FLAG_TIME) != 0;

@@ -73,3 +73,12 @@ def test_strerror_and_aux_bytes():
     ls = ss.aux_bytes(1 << 30, ss.SS_U64, "lowspace")
     assert ls - small >= (1 << 30) // 64 * 4                   # one 32-bit block prefix per 64 elements
     assert ls - small < (1 << 30) // 64 * 4 + (1 << 20)
+
+
+def test_line_count_limit_rejected_before_device_work():
+    import paper_2004_12532_amd as ss
+    split = ctypes.c_size_t(3)
+    p = ss.make_params(b=16)  # 64-byte u32 lines
+    rc = ss.lib.ss_partition_ex(ctypes.c_void_p(0x1000), (1 << 36) + 5, ss.SS_U32, 5, ctypes.byref(p), None, None,
+                                ctypes.byref(split), None)
+    assert rc == -1 and b"lines" in ss.lib.ss_last_error()

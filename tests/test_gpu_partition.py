@@ -273,3 +273,23 @@ def test_full_size_2p30_properties(ss):
     assert st["levels"] >= 2
     del t
     torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_more_than_2p32_elements_u32(ss):
+    """2^32 + 1000 uint32 keys (16 GiB): the 64-bit index paths, with 64-byte lines."""
+    torch = _torch()
+    n = (1 << 32) + 1000
+    t = workloads.keys_u32_torch(n, 99, "cuda")
+    pivot = 1 << 31
+    host_in = t.cpu().numpy().view(np.uint32)
+    count = oracle.count_less(host_in, pivot)
+    fp_in = oracle.fingerprint(host_in)
+    del host_in
+    split, st = ss.partition(t, pivot, stats=True, b=16)
+    assert split == count
+    host_out = t.cpu().numpy().view(np.uint32)
+    assert oracle.is_partitioned(host_out, pivot, split)
+    assert oracle.fingerprint(host_out) == fp_in
+    del t, host_out
+    torch.cuda.empty_cache()
