@@ -6,20 +6,30 @@
 // (absolute element indices into the base), its pivot, its number of groups
 // g_k at this level, and its split once found.  A level is four launches with
 // no host decision in between:
-//   k_bplan   per array: the level's geometry g_k from its region;
-//   k_bscan   one workgroup: exclusive scan of g_k -> the array's first item;
+//   k_binit / k_bstep  per array (one wavefront): fold the previous level's
+//             splitting positions of its groups into [v_min, v_max) -- a
+//             region left with one group or none is finished (split = v_min),
+//             otherwise it is the next region -- and plan the next level's
+//             geometry g_k from that region;
+//   k_bscan   one workgroup: exclusive scan of g_k -> the array's first item,
+//             staged through LDS so that every global access is coalesced;
 //   k_bfill   item map: item t -> array k (one wavefront per array);
 //   k_blevel  persistent: every workgroup takes items t = bid, bid + grid, ...,
 //             partitions group t - first_k of array k exactly as the
 //             single-array kernel does and writes the group's splitting
-//             position v;
-//   k_breduce per array: [v_min, v_max) over its items; a region left with
-//             one group or none is finished (split = v_min); otherwise it is
-//             the next level's region.
+//             position v.
+// The number of levels is planned on the host from the longest array (each
+// level shrinks a region by more than 16x once it spans several groups).  An
+// array still open after the last level -- unlikely, but not excluded by the
+// randomness of the offsets -- is finished by k_bcleanup, one workgroup per
+// such array running the serial block two-pointer exchange over its small
+// remaining region, so a call is a fixed chain of launches that never needs a
+// host decision.
 // Arrays that fit one group are whole-array tiles (g = 1) and finish at the
 // first level.  The chunk offsets depend on (seed, level, j, g) only, never on
 // an array's position in the batch, so an array gets the same bytes alone and
 // inside any batch.
+#include "ss_cleanup.h"
 #include "ss_common.h"
 #include "ss_device.h"
 #include "ss_internal.h"
@@ -40,75 +50,134 @@ struct BatchGeom {
     uint32_t level;
 };
 
+__device__ __forceinline__ uint32_t bnum(const BatchState &B)
+{
+    return B.count ? *B.count : B.num;
+}
+
+__device__ __forceinline__ uint32_t plan_groups(const BatchState &B, const BatchGeom &Gm, uint32_t k, uint64_t lo,
+                                                uint64_t hi)
+{
+    return plan_geo(lo - B.start[k], hi - B.start[k], Gm.log2b, Gm.s_max).g;
+}
+
+// First level: every array's region is the whole array.
 __global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
 {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= B.num)
+    if (k >= bnum(B))
         return;
     const uint64_t s = B.start[k], l = B.len[k];
     B.lo[k] = s;
     B.hi[k] = s + l;
     B.split[k] = l ? ~0ull : s;
+    B.g[k] = l ? plan_groups(B, Gm, k, s, s + l) : 0u;
 }
 
-__global__ void __launch_bounds__(256) k_bplan(BatchState B, BatchGeom Gm)
+// Later levels: fold the previous level's splitting positions of array k
+// (one wavefront per array), then plan the next level.
+__global__ void __launch_bounds__(256) k_bstep(BatchState B, BatchGeom Gm)
 {
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= B.num)
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= bnum(B))
         return;
-    uint32_t g = 0;
-    if (B.split[k] == ~0ull) {
-        const Geo G = plan_geo(B.lo[k] - B.start[k], B.hi[k] - B.start[k], Gm.log2b, Gm.s_max);
-        g = G.g;
+    const uint32_t g = B.g[k];
+    if (g == 0)
+        return;
+    const uint64_t f = B.first[k];
+    uint64_t mn = ~0ull, mx = 0;
+    for (uint32_t i = threadIdx.x & 63; i < g; i += 64) {
+        const uint64_t v = B.vout[f + i];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
     }
-    B.g[k] = g;
-}
-
-__global__ void __launch_bounds__(1024) k_bscan(BatchState B)
-{
-    __shared__ uint64_t wsum[16], wopen[16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint32_t per = (B.num + 1023) / 1024;
-    const uint32_t k0 = threadIdx.x * per;
-    uint64_t s = 0, open = 0;
-    for (uint32_t k = k0; k < k0 + per && k < B.num; k++) {
-        s += B.g[k];
-        open += B.g[k] != 0;
-    }
-    uint64_t inc = s, oinc = open;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = __shfl_up(inc, d, 64), z = __shfl_up(oinc, d, 64);
-        if (lane >= d) {
-            inc += y;
-            oinc += z;
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) {
+        if (g == 1 || !(mn < mx)) {
+            B.split[k] = mn;
+            B.g[k] = 0;
+        } else {
+            B.lo[k] = mn;
+            B.hi[k] = mx;
+            B.g[k] = plan_groups(B, Gm, k, mn, mx);
         }
     }
-    if (lane == 63) {
-        wsum[wid] = inc;
-        wopen[wid] = oinc;
+}
+
+// Exclusive scan of g over all arrays (first item of every array), the item
+// count ctl[0] and the count of open arrays ctl[1].  One workgroup; chunks of
+// kScanChunk entries are staged through LDS so that global reads and writes
+// are coalesced, and each thread scans kScanPer consecutive entries.
+constexpr int kScanNT = 1024, kScanPer = 8, kScanChunk = kScanNT * kScanPer;
+
+__global__ void __launch_bounds__(kScanNT) k_bscan(BatchState B)
+{
+    __shared__ uint64_t tile[kScanChunk];
+    __shared__ uint64_t wsum[kScanNT / 64], wopen[kScanNT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint64_t carry = 0, ocarry = 0;
+    const uint32_t num = bnum(B);
+    for (uint32_t c0 = 0; c0 < num; c0 += kScanChunk) {
+        const uint32_t m = num - c0 < (uint32_t)kScanChunk ? num - c0 : (uint32_t)kScanChunk;
+        for (uint32_t j = tid; j < m; j += kScanNT)
+            tile[j] = B.g[c0 + j];
+        __syncthreads();
+        uint64_t v[kScanPer], s = 0, open = 0;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const uint32_t j = tid * kScanPer + r;
+            v[r] = j < m ? tile[j] : 0;
+            s += v[r];
+            open += v[r] != 0;
+        }
+        uint64_t inc = s, oinc = open;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(inc, d, 64), z = __shfl_up(oinc, d, 64);
+            if (lane >= d) {
+                inc += y;
+                oinc += z;
+            }
+        }
+        if (lane == 63) {
+            wsum[wid] = inc;
+            wopen[wid] = oinc;
+        }
+        __syncthreads();
+        uint64_t off = carry, tot = 0, otot = 0;
+        for (int w = 0; w < kScanNT / 64; w++) {
+            if (w < wid)
+                off += wsum[w];
+            tot += wsum[w];
+            otot += wopen[w];
+        }
+        uint64_t run = off + inc - s;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const uint32_t j = tid * kScanPer + r;
+            if (j < m)
+                tile[j] = run;
+            run += v[r];
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < m; j += kScanNT)
+            B.first[c0 + j] = tile[j];
+        carry += tot;
+        ocarry += otot;
+        __syncthreads();  // tile and wsum are rewritten by the next chunk
     }
-    __syncthreads();
-    uint64_t off = 0, ooff = 0;
-    for (int w = 0; w < wid; w++) {
-        off += wsum[w];
-        ooff += wopen[w];
-    }
-    uint64_t run = off + inc - s;
-    for (uint32_t k = k0; k < k0 + per && k < B.num; k++) {
-        B.first[k] = run;
-        run += B.g[k];
-    }
-    if (threadIdx.x == 1023) {
-        B.first[B.num] = run;
-        B.ctl[0] = run;
-        B.ctl[1] = ooff + oinc;
+    if (tid == 0) {
+        B.first[num] = carry;
+        B.ctl[0] = carry;
+        B.ctl[1] = ocarry;
     }
 }
 
 __global__ void __launch_bounds__(256) k_bfill(BatchState B)
 {
     const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= B.num)
+    if (k >= bnum(B))
         return;
     const uint64_t f = B.first[k];
     const uint32_t g = B.g[k];
@@ -151,14 +220,15 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
             xoff[j] = G.g > 1 ? chunk_offset(Gm.seed, Gm.level, j, G.g) : 0u;
         __syncthreads();
         v4u buf[NV];
+        typename Ctx::Mask m;
         const bool fast = x.fast(i);
         uint32_t c;
         if (fast) {
-            x.template load<true>(buf, i);
-            c = x.template partition<true>(buf, i);
+            x.template load<true>(buf, i, m);
+            c = x.template partition<true>(buf, i, m);
         } else {
-            x.template load<false>(buf, i);
-            c = x.template partition<false>(buf, i);
+            x.template load<false>(buf, i, m);
+            c = x.template partition<false>(buf, i, m);
         }
         if (tid == 0) {
             uint64_t vi;
@@ -175,37 +245,27 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
     }
 }
 
-__global__ void __launch_bounds__(256) k_breduce(BatchState B)
+// Arrays still open after the last level: one workgroup each partitions the
+// remaining region serially (block two-pointer exchange).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_bcleanup(BatchState B, BatchGeom Gm)
 {
-    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= B.num)
-        return;
-    const uint32_t g = B.g[k];
-    if (g == 0)
-        return;
-    const uint64_t f = B.first[k];
-    uint64_t mn = ~0ull, mx = 0;
-    for (uint32_t i = threadIdx.x & 63; i < g; i += 64) {
-        const uint64_t v = B.vout[f + i];
-        mn = v < mn ? v : mn;
-        mx = v > mx ? v : mx;
-    }
-    mn = wave_min(mn);
-    mx = wave_max(mx);
-    if ((threadIdx.x & 63) == 0) {
-        if (g == 1 || !(mn < mx)) {
-            B.split[k] = mn;
-        } else {
-            B.lo[k] = mn;
-            B.hi[k] = mx;
-        }
+    __shared__ CleanupSmem<T, 1024, 16384> S;
+    const uint32_t num = bnum(B);
+    for (uint32_t k = blockIdx.x; k < num; k += gridDim.x) {
+        if (B.split[k] != ~0ull)
+            continue;
+        const uint64_t sp = cleanup_region<T, 1024, 16384>(reinterpret_cast<T *>(Gm.base), B.pivot[k], B.lo[k],
+                                                            B.hi[k], S);
+        if (threadIdx.x == 0)
+            B.split[k] = sp;
     }
 }
 
 __global__ void __launch_bounds__(256) k_bfinish(BatchState B, uint64_t *d_splits)
 {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= B.num)
+    if (k >= bnum(B))
         return;
     const uint64_t s = B.split[k];
     d_splits[k] = s == ~0ull ? ~0ull : s - B.start[k];
@@ -262,14 +322,30 @@ const BVariant *pick_bvariant(int dtype, uint32_t tile)
 
 }  // namespace
 
-// Run the batched recursion for `num` arrays whose start/len are already in
-// device memory (B.start, B.len).  Writes d_splits (relative to each start,
-// UINT64_MAX if unfinished).  When `sync`, continues from the host until every
-// array is finished and fills *open_left with 0.
-int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64_t items_cap, hipStream_t st,
-                 uint64_t *d_splits, bool sync, uint32_t *launches, uint32_t *levels_run)
+// Levels of the batched recursion for arrays of at most max_len elements:
+// one level finishes a region of one group; a region of several groups
+// shrinks by well over 16x per level (its middle region is a few percent of
+// it plus at most one group's worth of lines), so the chain plans
+// 2 + ceil(log16(max_len / group)) levels.  A region still open after them is
+// finished by the cleanup kernel.
+uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems)
 {
-    (void)items_cap;
+    uint32_t lv = 1;
+    uint64_t r = max_len;
+    while (r > tile_elems && lv < 16) {
+        r = r / 16;
+        lv++;
+    }
+    return lv == 1 ? 1u : lv + 1;
+}
+
+// Run the batched recursion for `num` arrays whose start/len are already in
+// device memory (B.start, B.len): `levels` persistent level launches, then
+// the cleanup of any array still open, then (if d_splits) the splits
+// relative to each start.  A fixed chain of launches with no host decision.
+int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint32_t levels, hipStream_t st,
+                 uint64_t *d_splits, uint32_t *launches)
+{
     hipError_t e;
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
@@ -278,9 +354,6 @@ int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64
     int rc = device_info(dev, &cus, &lds);
     if (rc)
         return rc;
-    Workspace *ws = nullptr;
-    if ((rc = get_workspace(dev, st, &ws)))
-        return rc;
     const uint32_t tile = R.engine == SS_ENGINE_REGS && R.tile ? R.tile : 131072u;
     const BVariant *V = pick_bvariant(dtype, tile);
     if (!V)
@@ -288,57 +361,47 @@ int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64
     int occ = 0;
     if ((rc = occupancy(dev, V->fn(), V->nt, &occ)))
         return rc;
-    uint32_t P = (uint32_t)(occ * cus);
+    const uint32_t P = (uint32_t)(occ * cus);
     BatchGeom Gm;
     Gm.base = base;
     Gm.w = R.w;
     Gm.log2b = R.log2b;
     Gm.s_max = (uint32_t)(tile / ((uint64_t)R.b * R.w));
     Gm.seed = R.seed;
+    Gm.level = 0;
     const uint32_t nb256 = (B.num + 255) / 256, nb4 = (B.num + 3) / 4;
-    hipLaunchKernelGGL(k_binit, dim3(nb256), dim3(256), 0, st, B, Gm);
-    (*launches)++;
-    uint32_t level = 0;
-    for (;;) {
-        for (uint32_t k = 0; k < R.levels; k++, level++) {
-            Gm.level = level;
-            hipLaunchKernelGGL(k_bplan, dim3(nb256), dim3(256), 0, st, B, Gm);
-            hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, B);
-            hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
-            if ((e = V->launch(P, B, Gm, st)) != hipSuccess)
-                return fail_device(e, "batched level launch");
-            hipLaunchKernelGGL(k_breduce, dim3(nb4), dim3(256), 0, st, B);
-            *launches += 5;
-        }
-        *levels_run = level;
-        // open arrays after the last reduce: plan once more to count them
+    if (levels < 1)
+        levels = 1;
+    for (uint32_t level = 0; level < levels; level++) {
         Gm.level = level;
-        hipLaunchKernelGGL(k_bplan, dim3(nb256), dim3(256), 0, st, B, Gm);
-        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, B);
-        *launches += 2;
-        if ((e = hipGetLastError()) != hipSuccess)
-            return fail_device(e, "batched launch");
-        if (!sync)
-            break;
-        if ((e = hipMemcpyAsync(ws->host, B.ctl, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
-            return fail_device(e, "hipMemcpyAsync");
-        if ((e = hipStreamSynchronize(st)) != hipSuccess)
-            return fail_device(e, "hipStreamSynchronize");
-        if (((volatile uint64_t *)ws->host)[1] == 0)
-            break;
-        if (level >= kHostLevelCap)
-            return fail_msg(SS_EDEVICE, "batched recursion did not converge");
+        if (level == 0)
+            hipLaunchKernelGGL(k_binit, dim3(nb256), dim3(256), 0, st, B, Gm);
+        else
+            hipLaunchKernelGGL(k_bstep, dim3(nb4), dim3(256), 0, st, B, Gm);
+        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kScanNT), 0, st, B);
+        hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
+        if ((e = V->launch(P, B, Gm, st)) != hipSuccess)
+            return fail_device(e, "batched level launch");
+        *launches += 4;
     }
+    Gm.level = levels;
+    hipLaunchKernelGGL(k_bstep, dim3(nb4), dim3(256), 0, st, B, Gm);
+    const uint32_t ncl = B.num < 4096u ? B.num : 4096u;
+    switch (dtype) {
+    case SS_U32: hipLaunchKernelGGL(k_bcleanup<uint32_t>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
+    case SS_U64: hipLaunchKernelGGL(k_bcleanup<uint64_t>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
+    default: hipLaunchKernelGGL(k_bcleanup<KV>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
+    }
+    *launches += 2;
     if (d_splits) {
         hipLaunchKernelGGL(k_bfinish, dim3(nb256), dim3(256), 0, st, B, d_splits);
         (*launches)++;
     }
     if ((e = hipGetLastError()) != hipSuccess)
-        return fail_device(e, "batched finish launch");
+        return fail_device(e, "batched launch");
     return SS_OK;
 }
 
-// Device state for `num` arrays (grown on demand, per device and stream).
 int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage)
 {
     std::lock_guard<std::mutex> lk(g_b_mu);
@@ -389,6 +452,7 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
     B->g = reinterpret_cast<uint32_t *>(p);
     p += (num + 1) / 2 + 1;
     B->imap = reinterpret_cast<uint32_t *>(p);
+    B->count = nullptr;
     B->num = num;
     *host_stage = w.host;
     return SS_OK;
@@ -418,11 +482,13 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
     if (R.engine != SS_ENGINE_REGS)
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses the register engine");
-    if (!p || !p->max_levels)
-        R.levels = 6;
-    for (size_t k = 0; k < num; k++)
+    uint64_t max_len = 0;
+    for (size_t k = 0; k < num; k++) {
         if ((rc = check_lines(lens[k], R)))
             return rc;
+        max_len = lens[k] > max_len ? lens[k] : max_len;
+    }
+    const uint32_t levels = p && p->max_levels ? R.levels : batched_levels(max_len, R.tile / R.w);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int dev = 0;
@@ -443,7 +509,6 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         return fail_device(e, "hipMemcpyAsync");
     RunOut ro;
     std::memset(&ro, 0, sizeof(ro));
-    const bool sync = stats != nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     const bool timing = (R.flags & SS_FLAG_TIME) != 0;
     if (timing) {
@@ -451,9 +516,7 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
             return fail_msg(SS_EDEVICE, "hipEventCreate");
         (void)hipEventRecord(t0, st);
     }
-    uint32_t levels_run = 0;
-    rc = batched_core((char *)d_base, dtype, R, B, items_cap, st, d_splits, sync || timing, &ro.launches,
-                      &levels_run);
+    rc = batched_core((char *)d_base, dtype, R, B, levels, st, d_splits, &ro.launches);
     if (rc)
         return rc;
     if (timing) {
@@ -469,7 +532,7 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return fail_device(e, "hipStreamSynchronize");
         fill_stats(stats, ro, R, dtype);
-        stats->levels = levels_run;
+        stats->levels = levels;
         std::lock_guard<std::mutex> lk(g_b_mu);
         stats->aux_bytes = g_b[std::make_pair(dev, stream)].dev_bytes;
     }

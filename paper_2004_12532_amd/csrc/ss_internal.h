@@ -105,12 +105,14 @@ struct BatchState {
     uint32_t *imap;    // item -> array
     uint64_t *vout;    // item -> splitting position
     uint64_t *ctl;     // [0] items of the current level, [1] open arrays
-    uint32_t num;
+    const uint32_t *count;  // device word holding the number of arrays (nullable: then num)
+    uint32_t num;      // number of arrays, or the capacity when count is set (sizes the grids)
 };
 int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage);
 uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems);
-int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint64_t items_cap, hipStream_t st,
-                 uint64_t *d_splits, bool sync, uint32_t *launches, uint32_t *levels_run);
+uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems);
+int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint32_t levels, hipStream_t st,
+                 uint64_t *d_splits, uint32_t *launches);
 
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats);

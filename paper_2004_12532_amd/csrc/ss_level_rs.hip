@@ -105,16 +105,17 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             vmax = vi > vmax ? vi : vmax;
         }
     };
-    auto load_any = [&](v4u (&buf)[NV], uint32_t i) -> bool {
+    using Mask = typename Ctx::Mask;
+    auto load_any = [&](v4u (&buf)[NV], uint32_t i, Mask &m) -> bool {
         const bool f = x.fast(i);
         if (f)
-            x.template load<true>(buf, i);
+            x.template load<true>(buf, i, m);
         else
-            x.template load<false>(buf, i);
+            x.template load<false>(buf, i, m);
         return f;
     };
-    auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f) -> uint32_t {
-        return f ? x.template partition<true>(buf, i) : x.template partition<false>(buf, i);
+    auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f, const Mask &m) -> uint32_t {
+        return f ? x.template partition<true>(buf, i, m) : x.template partition<false>(buf, i, m);
     };
 
     const uint32_t step = gridDim.x;
@@ -125,35 +126,37 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     if (!DB) {
         // One register buffer: the next group's loads are issued after this group's stores.
         v4u buf[NV];
+        Mask m;
         uint32_t i = first;
         bool fast = false;
         if (i < G.g)
-            fast = load_any(buf, i);
+            fast = load_any(buf, i, m);
         while (i < G.g) {
-            fold(part_any(buf, i, fast), i);
+            fold(part_any(buf, i, fast, m), i);
             i += step;
             if (i < G.g)
-                fast = load_any(buf, i);
+                fast = load_any(buf, i, m);
             __syncthreads();  // the counts are rewritten by the next group
         }
     } else {
         // Two register buffers: the next group's loads are issued before this group is partitioned.
         v4u ba[NV], bb[NV];
+        Mask ma, mb;
         uint32_t i = first;
         bool fa = false, fb = false;
         if (i < G.g)
-            fa = load_any(ba, i);
+            fa = load_any(ba, i, ma);
         while (i < G.g) {
             if (i + step < G.g)
-                fb = load_any(bb, i + step);
-            fold(part_any(ba, i, fa), i);
+                fb = load_any(bb, i + step, mb);
+            fold(part_any(ba, i, fa, ma), i);
             __syncthreads();
             i += step;
             if (i >= G.g)
                 break;
             if (i + step < G.g)
-                fa = load_any(ba, i + step);
-            fold(part_any(bb, i, fb), i);
+                fa = load_any(ba, i + step, ma);
+            fold(part_any(bb, i, fb, mb), i);
             __syncthreads();
             i += step;
         }

@@ -78,9 +78,19 @@ struct LevelCtx {
         return ((uint64_t)(line_of(s - 1, i) + 1) << log2b) <= real_end;
     }
 
+    // Which slots of this thread's vectors are real elements, and which are
+    // virtual predecessors in front of the region (bit r * V + e for element
+    // e of vector r).  Slots past the region's end, and vectors past the
+    // group's last line, are virtual successors: neither bit is set.
+    struct Mask {
+        uint64_t real, front;
+    };
+
     template <bool FAST>
-    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i) const
+    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i, Mask &m) const
     {
+        m.real = 0;
+        m.front = 0;
 #pragma unroll
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
@@ -92,11 +102,18 @@ struct LevelCtx {
                     const uint64_t e0 = vec_start(q, i);
                     if (e0 >= fp && e0 + V <= real_end) {
                         buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(e0));
+                        m.real |= (uint64_t)((1u << V) - 1) << (r * V);
                     } else {
 #pragma unroll
-                        for (int e = 0; e < V; e++)
-                            if (e0 + e >= fp && e0 + e < real_end)
-                                Elem<T>::load1(buf[r], e, elem_ptr(e0 + e));
+                        for (int e = 0; e < V; e++) {
+                            const uint64_t vp = e0 + e;
+                            if (vp >= fp && vp < real_end) {
+                                Elem<T>::load1(buf[r], e, elem_ptr(vp));
+                                m.real |= 1ull << (r * V + e);
+                            } else if (vp < fp) {
+                                m.front |= 1ull << (r * V + e);
+                            }
+                        }
                     }
                 }
             }
@@ -105,36 +122,27 @@ struct LevelCtx {
 
     // Decider bits of vector r; virtual front elements count as predecessors.
     template <bool FAST>
-    __device__ __forceinline__ uint32_t bits_of(const v4u &v, int r, uint32_t i) const
+    __device__ __forceinline__ uint32_t bits_of(const v4u &v, int r, const Mask &m) const
     {
         uint32_t bits = 0;
-        if (FAST) {
 #pragma unroll
-            for (int e = 0; e < V; e++)
-                bits |= (uint32_t)(Elem<T>::key(v, e) < pivot) << e;
-        } else {
-            const uint32_t q = r * NT + tid;
-            if (q < nvec) {
-                const uint64_t e0 = vec_start(q, i);
-#pragma unroll
-                for (int e = 0; e < V; e++) {
-                    const uint64_t vp = e0 + e;
-                    const bool real = vp >= fp && vp < real_end;
-                    bits |= (uint32_t)(real ? Elem<T>::key(v, e) < pivot : vp < fp) << e;
-                }
-            }
+        for (int e = 0; e < V; e++)
+            bits |= (uint32_t)(Elem<T>::key(v, e) < pivot) << e;
+        if (!FAST) {
+            constexpr uint32_t VM = (1u << V) - 1;
+            bits = (bits & (uint32_t)(m.real >> (r * V)) & VM) | ((uint32_t)(m.front >> (r * V)) & VM);
         }
         return bits;
     }
 
     // Stable partition of group i; returns its predecessor count c_i.
     template <bool FAST>
-    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i) const
+    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i, const Mask &m) const
     {
         uint64_t pb = 0;
 #pragma unroll
         for (int r = 0; r < NV; r++) {
-            const uint32_t bits = bits_of<FAST>(buf[r], r, i);
+            const uint32_t bits = bits_of<FAST>(buf[r], r, m);
             pb |= (uint64_t)bits << (r * V);
             uint32_t tot = 0;
 #pragma unroll
@@ -182,16 +190,13 @@ struct LevelCtx {
 #pragma unroll
             for (int e = 0; e < V; e++)
                 rp += lanes_below(__ballot((bits >> e) & 1));
-            uint64_t e0 = 0;
-            if (!FAST && q < nvec)
-                e0 = vec_start(q, i);
 #pragma unroll
             for (int e = 0; e < V; e++) {
                 const bool p = (bits >> e) & 1;
                 const uint32_t slot = q * V + e;
                 const uint32_t d = p ? rp : c + slot - rp;
                 rp += p;
-                if (FAST || (q < nvec && e0 + e >= fp && e0 + e < real_end)) {
+                if (FAST || ((m.real >> (r * V + e)) & 1)) {
                     const uint64_t vd = ((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1));
                     store_elem<NTMP, T>(buf[r], e, elem_ptr(vd));
                 }

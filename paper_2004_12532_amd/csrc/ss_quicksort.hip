@@ -7,23 +7,32 @@
 // Striding partition, and the short segments are finished by a
 // workgroup-local radix sort in LDS.
 //
-// Per level:
-//   * k_qpivot: median of the keys at lo, lo + len/2 and hi - 1 of every
-//     segment (median-of-3);
-//   * batched partition by key < p;
-//   * a segment with no key below p (p is its minimum) is partitioned again
-//     by key <= p: its equal keys form a block that is final, so every level
-//     makes progress even when keys repeat; otherwise both parts are strictly
-//     smaller than the segment because p itself is on the right;
-//   * children longer than the leaf size become the next level's segments,
-//     the others (of two elements or more) leaves.
-// Leaves: one workgroup per leaf; least-significant-digit radix sort with
-// 8-bit digits over the key (KV16 records move with their key).  Within a
-// pass, each wavefront ranks 64 elements at a time: eight ballots give each
-// lane the mask of lanes holding the same digit, the lowest lane of that
-// mask advances the wavefront's counter for the digit, and a scan over
-// (digit, wavefront) turns the counters into destinations.  The sort is
-// stable and needs no atomics.
+// The segment lists live on the device and a level is a fixed chain of
+// launches, so the host never waits for a level before issuing the next one:
+//   * k_qprep: the pivot of every segment -- the median of the keys at its
+//     first, middle and last positions, or the pivot carried over for a
+//     second pass (below);
+//   * the batched partition (ss_batched.hip) by key < pivot;
+//   * k_qchildren: a segment with no key below its pivot p (p is its
+//     minimum) goes to the next level with pivot p + 1, i.e. it is
+//     partitioned by key <= p and its block of copies of p becomes final, so
+//     every level makes progress even when keys repeat; otherwise both parts
+//     are strictly smaller than the segment because p itself is on the
+//     right.  Children longer than the leaf size are appended to the next
+//     level's list, shorter ones (two elements or more) to this level's leaf
+//     list (appends use atomic counters; an element's result does not depend
+//     on its segment's place in a list);
+//   * k_qleaf: every leaf of the level is sorted by one workgroup.
+// The host keeps one level in flight ahead of the one it inspects: after
+// level L completes it reads the number and the longest length of level
+// L + 1's segments from mapped memory, and issues level L + 2 with the
+// number of partition levels that the longest segment needs.
+// Leaves: least-significant-digit radix sort with 8-bit digits over the key
+// (KV16 records move with their key).  Within a pass, each wavefront ranks 64
+// elements at a time: eight ballots give each lane the mask of lanes holding
+// the same digit, the lowest lane of that mask advances the wavefront's
+// counter for the digit, and a scan over (digit, wavefront) turns the
+// counters into destinations.  The sort is stable and needs no atomics.
 #include "ss_common.h"
 #include "ss_device.h"
 #include "ss_internal.h"
@@ -69,9 +78,9 @@ struct Digit {
     __device__ static __forceinline__ uint32_t of(const T &x, uint32_t sh) { return (uint32_t)(qkey(x) >> sh) & 255u; }
 };
 
-// One workgroup sorts leaf blockIdx.x (at most CAP elements) by key.
+// One workgroup (1024 threads) sorts A[0, n), n <= CAP, by key.
 template <typename T, int CAP, int KEYBITS>
-__global__ void __launch_bounds__(1024) k_qleaf(char *base, const uint64_t *start, const uint64_t *len)
+__device__ void qleaf_sort(T *A, uint32_t n)
 {
     constexpr int NT = 1024, NW = NT / 64;
     constexpr int E = CAP / NT;  // elements per thread
@@ -80,8 +89,6 @@ __global__ void __launch_bounds__(1024) k_qleaf(char *base, const uint64_t *star
     __shared__ uint32_t dig_base[256];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    T *A = reinterpret_cast<T *>(base) + start[blockIdx.x];
-    const uint32_t n = (uint32_t)len[blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1;
 
     // Striped arrangement: element r of thread (wid, lane) is at
@@ -165,12 +172,40 @@ __global__ void __launch_bounds__(1024) k_qleaf(char *base, const uint64_t *star
         if (valid[r])
             A[idx] = x[r];
     }
+    __syncthreads();  // LDS is reused by the next leaf
 }
+
+// Leaves are taken by workgroups in turn (leaf b, b + grid, ...); each leaf
+// (at most CAP elements) is sorted by key by one workgroup.  The number of
+// leaves is *count when count is set, else nleaves.  When pub_dst is set,
+// workgroup 0 first writes the quicksort's per-level report to the host.
+struct QLeafArgs {
+    char *base;
+    const uint64_t *start, *len;
+    const uint32_t *count;
+    uint32_t nleaves;
+    const uint32_t *pub_count;  // report: pub_dst[0] = *pub_count, pub_dst[1] = *pub_max
+    const uint64_t *pub_max;
+    uint64_t *pub_dst;
+};
+
+template <typename T, int CAP, int KEYBITS>
+__global__ void __launch_bounds__(1024) k_qleaf(QLeafArgs a)
+{
+    if (a.pub_dst && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.pub_dst[0] = *a.pub_count;
+        a.pub_dst[1] = *a.pub_max;
+    }
+    const uint32_t nleaves = a.count ? *a.count : a.nleaves;
+    for (uint32_t leaf = blockIdx.x; leaf < nleaves; leaf += gridDim.x)
+        qleaf_sort<T, CAP, KEYBITS>(reinterpret_cast<T *>(a.base) + a.start[leaf], (uint32_t)a.len[leaf]);
+}
+
 
 namespace {
 
 struct QsWork {
-    uint64_t *dev = nullptr;     // pivots (second pass), leaf list
+    uint64_t *dev = nullptr;     // uploaded segment lists
     size_t dev_words = 0;
     uint64_t *host = nullptr;    // mapped: pivots, splits
     uint64_t *host_dev = nullptr;
@@ -236,27 +271,206 @@ hipError_t launch_qpivot(const char *base, const BatchState &B, uint32_t m, uint
     return hipGetLastError();
 }
 
-hipError_t launch_qleaf(int dtype, char *base, const uint64_t *start, const uint64_t *len, uint32_t nleaves,
-                        hipStream_t st)
+int qleaf_grid(int dtype)
 {
+    static int grid[4] = {0, 0, 0, 0};
+    int &g = grid[dtype & 3];
+    if (!g) {
+        int dev = 0, cus = 0, lds = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &cus, &lds) != SS_OK)
+            return 256;
+        const void *fn = dtype == SS_U32   ? reinterpret_cast<const void *>(&k_qleaf<uint32_t, 16384, 32>)
+                         : dtype == SS_U64 ? reinterpret_cast<const void *>(&k_qleaf<uint64_t, 16384, 64>)
+                                           : reinterpret_cast<const void *>(&k_qleaf<KV, 8192, 64>);
+        if (occupancy(dev, fn, 1024, &occ) != SS_OK)
+            return 256;
+        g = occ * cus;
+    }
+    return g;
+}
+
+hipError_t launch_qleaf(int dtype, const QLeafArgs &a, hipStream_t st)
+{
+    uint32_t grid = (uint32_t)qleaf_grid(dtype);
+    if (!a.count && a.nleaves < grid)
+        grid = a.nleaves ? a.nleaves : 1u;
     switch (dtype) {
-    case SS_U32:
-        hipLaunchKernelGGL((k_qleaf<uint32_t, 16384, 32>), dim3(nleaves), dim3(1024), 0, st, base, start, len);
-        break;
-    case SS_U64:
-        hipLaunchKernelGGL((k_qleaf<uint64_t, 16384, 64>), dim3(nleaves), dim3(1024), 0, st, base, start, len);
-        break;
-    default:
-        hipLaunchKernelGGL((k_qleaf<KV, 8192, 64>), dim3(nleaves), dim3(1024), 0, st, base, start, len);
-        break;
+    case SS_U32: hipLaunchKernelGGL((k_qleaf<uint32_t, 16384, 32>), dim3(grid), dim3(1024), 0, st, a); break;
+    case SS_U64: hipLaunchKernelGGL((k_qleaf<uint64_t, 16384, 64>), dim3(grid), dim3(1024), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_qleaf<KV, 8192, 64>), dim3(grid), dim3(1024), 0, st, a); break;
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ device-driven levels
+
+// Segment lists: start, len and carried pivot (0: choose the median of 3;
+// otherwise the pivot of a key <= p pass, stored as p + 1).
+struct SegList {
+    uint64_t *start, *len, *pv;
+    uint32_t *count;
+};
+
+struct QsCtl {
+    uint64_t *piv;         // this level's pivots
+    uint32_t *leaf_count;  // leaves of this level
+    uint64_t *leaf_start, *leaf_len;
+    uint64_t *report;      // [0] segments of the next level, [1] the longest of them
+    uint32_t *overflow;    // set if a list capacity would be exceeded (never, by the bounds below)
+    uint32_t cap_segs, cap_leaves;
+    uint64_t leaf_cap;     // segments up to this length are leaves
+};
+
+__global__ void k_qinit(SegList L, QsCtl C, uint64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        L.start[0] = 0;
+        L.len[0] = n;
+        L.pv[0] = 0;
+        *L.count = 1;
+        *C.overflow = 0;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_qprep(const char *base, SegList cur, SegList nxt, QsCtl C)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k == 0) {
+        *nxt.count = 0;
+        *C.leaf_count = 0;
+        C.report[1] = 0;
+    }
+    if (k >= *cur.count)
+        return;
+    if (cur.pv[k]) {
+        C.piv[k] = cur.pv[k];
+        return;
+    }
+    const T *A = reinterpret_cast<const T *>(base) + cur.start[k];
+    const uint64_t l = cur.len[k];
+    uint64_t a = qkey(A[0]), b = qkey(A[l / 2]), c = qkey(A[l - 1]);
+    if (a > b) {
+        const uint64_t t = a;
+        a = b;
+        b = t;
+    }
+    if (b > c)
+        b = c;
+    C.piv[k] = a > b ? a : b;  // median of the three
+}
+
+__device__ __forceinline__ void q_emit(const SegList &nxt, const QsCtl &C, uint64_t s, uint64_t l, uint64_t pv)
+{
+    if (l > C.leaf_cap) {
+        const uint32_t i = atomicAdd(nxt.count, 1u);
+        if (i >= C.cap_segs) {
+            atomicOr(C.overflow, 1u);
+            return;
+        }
+        nxt.start[i] = s;
+        nxt.len[i] = l;
+        nxt.pv[i] = pv;
+        atomicMax(reinterpret_cast<unsigned long long *>(&C.report[1]), (unsigned long long)l);
+    } else if (l >= 2) {
+        const uint32_t i = atomicAdd(C.leaf_count, 1u);
+        if (i >= C.cap_leaves) {
+            atomicOr(C.overflow, 1u);
+            return;
+        }
+        C.leaf_start[i] = s;
+        C.leaf_len[i] = l;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_qchildren(SegList cur, SegList nxt, QsCtl C, const uint64_t *split)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < *cur.count) {
+        const uint64_t s = cur.start[k], l = cur.len[k], rel = split[k] - s, p = C.piv[k];
+        if (split[k] < s || rel > l) {  // an unfinished partition (cannot happen: the chain ends with a cleanup)
+            atomicOr(C.overflow, 2u);
+            return;
+        }
+        if (!cur.pv[k] && rel == 0) {
+            if (p != ~0ull)
+                q_emit(nxt, C, s, l, p + 1);  // next level: key <= p
+            // p = 2^64 - 1 is the minimum: every key equals it, the segment is sorted
+        } else {
+            if (!cur.pv[k])
+                q_emit(nxt, C, s, rel, 0);
+            // after a key <= p pass, [s, s + rel) holds only copies of p and is final
+            q_emit(nxt, C, s + rel, l - rel, 0);
+        }
+    }
 }
 
 }  // namespace
 
 uint64_t quicksort_leaf_cap(int dtype) { return dtype == SS_KV16 ? 8192 : 16384; }
 
+namespace {
+
+// Device workspace of the device-driven quicksort, cached per (device,
+// stream) and grown on demand.
+struct QsDev {
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    uint64_t *rep = nullptr;      // mapped host: per level {segments of the next level, longest}
+    uint64_t *rep_dev = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+std::mutex g_qd_mu;
+std::map<std::pair<int, void *>, QsDev> g_qd;
+
+constexpr uint32_t kMaxQsLevels = 4096;
+
+int qs_dev_reserve(int dev, void *stream, size_t bytes, QsDev **out)
+{
+    std::lock_guard<std::mutex> lk(g_qd_mu);
+    QsDev &w = g_qd[std::make_pair(dev, stream)];
+    hipError_t e;
+    if (w.dev_bytes < bytes) {
+        if (w.dev)
+            (void)hipFree(w.dev);
+        w.dev = nullptr;
+        w.dev_bytes = 0;
+        if ((e = hipMalloc((void **)&w.dev, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_msg(SS_ENOMEM, std::string("quicksort workspace: ") + hipGetErrorString(e));
+        }
+        w.dev_bytes = bytes;
+    }
+    if (!w.rep) {
+        if ((e = hipHostMalloc((void **)&w.rep, 2 * kMaxQsLevels * sizeof(uint64_t),
+                               hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess) {
+            (void)hipGetLastError();
+            w.rep = nullptr;
+            return fail_msg(SS_ENOMEM, std::string("quicksort report buffer: ") + hipGetErrorString(e));
+        }
+        if ((e = hipHostGetDevicePointer((void **)&w.rep_dev, w.rep, 0)) != hipSuccess)
+            return fail_device(e, "hipHostGetDevicePointer");
+        for (auto &ev : w.ev)
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return fail_device(e, "hipEventCreate");
+    }
+    *out = &w;
+    return SS_OK;
+}
+
+template <typename T>
+hipError_t launch_qprep(const char *base, const SegList &cur, const SegList &nxt, const QsCtl &C, uint32_t grid,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qprep<T>, dim3(grid), dim3(256), 0, st, base, cur, nxt, C);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Quicksort of base[0, n).  Segments longer than the leaf capacity are
+// disjoint, so a level holds at most n / (cap + 1) of them and at most twice
+// as many leaves; the batched state is sized for that.
 int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_t st, uint32_t *levels_out,
                   uint32_t *launches)
 {
@@ -264,146 +478,118 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
         return fail_device(e, "hipGetDevice");
+    *levels_out = 0;
+    if (n < 2)
+        return SS_OK;
     const uint64_t cap = quicksort_leaf_cap(dtype);
-    const size_t max_segs = n / cap + 2;
-    const size_t max_leaves = 2 * max_segs * 64 + 16;
-    QsWork *w = nullptr;
-    int rc = qs_reserve(dev, st, max_segs + 2 * max_leaves, 2 * max_segs, 2 * max_leaves + 3 * max_segs, &w);
+    const uint64_t tile_elems = R.tile / R.w;
+    const uint64_t capS = n / (cap + 1) + 2, capL = 2 * capS + 2;
+    const uint64_t items = n / tile_elems + 3 * capS + 64;
+    // word layout of the workspace
+    const size_t words = 2 * 3 * capS + capS /*piv*/ + 2 * capL /*leaves*/ + 3 * capS /*lo, hi, split*/ +
+                         (capS + 1) /*first*/ + items /*vout*/ + (capS + 1) / 2 + 1 /*g*/ + (items + 1) / 2 /*imap*/ +
+                         8 /*ctl*/ + 8 /*counts, report, overflow*/;
+    QsDev *W = nullptr;
+    int rc = qs_dev_reserve(dev, st, words * sizeof(uint64_t), &W);
     if (rc)
         return rc;
-    uint64_t *piv2_dev = w->dev;                      // pivots of the second pass
-    uint64_t *leaf_dev = w->dev + max_segs;           // leaves: starts then lengths
-    uint64_t *piv_host = w->host, *piv_host_dev = w->host_dev;
-    uint64_t *split_host = w->host + max_segs, *split_host_dev = w->host_dev + max_segs;
-
-    std::vector<uint64_t> seg_start, seg_len, leaf_start, leaf_len;
-    if (n > cap) {
-        seg_start.push_back(0);
-        seg_len.push_back(n);
-    } else if (n >= 2) {
-        leaf_start.push_back(0);
-        leaf_len.push_back(n);
-    }
-    uint32_t levels = 0;
-    std::vector<uint64_t> nxt_start, nxt_len, eq_idx;
-    auto add_child = [&](uint64_t s, uint64_t l) {
-        if (l > cap) {
-            nxt_start.push_back(s);
-            nxt_len.push_back(l);
-        } else if (l >= 2) {
-            leaf_start.push_back(s);
-            leaf_len.push_back(l);
-        }
+    uint64_t *p = reinterpret_cast<uint64_t *>(W->dev);
+    auto take = [&](size_t nw) {
+        uint64_t *q = p;
+        p += nw;
+        return q;
     };
-    while (!seg_start.empty()) {
-        const uint32_t m = (uint32_t)seg_start.size();
-        const uint64_t icap = batched_items_cap(seg_len.data(), m, R.tile / R.w);
-        BatchState B;
-        uint64_t *bstage = nullptr;
-        if ((rc = batched_state(dev, st, m, icap, &B, &bstage)))
-            return rc;
-        if ((e = hipStreamSynchronize(st)) != hipSuccess)
-            return fail_device(e, "hipStreamSynchronize");
-        std::memcpy(bstage, seg_start.data(), m * sizeof(uint64_t));
-        std::memcpy(bstage + m, seg_len.data(), m * sizeof(uint64_t));
-        if ((e = hipMemcpyAsync(B.start, bstage, 2 * (size_t)m * sizeof(uint64_t), hipMemcpyHostToDevice, st)) !=
-            hipSuccess)
-            return fail_device(e, "hipMemcpyAsync");
-        // median-of-3 pivots, on the device and in mapped host memory
-        switch (dtype) {
-        case SS_U32: e = launch_qpivot<uint32_t>(base, B, m, piv2_dev, piv_host_dev, st); break;
-        case SS_U64: e = launch_qpivot<uint64_t>(base, B, m, piv2_dev, piv_host_dev, st); break;
-        default: e = launch_qpivot<KV>(base, B, m, piv2_dev, piv_host_dev, st); break;
-        }
-        if (e != hipSuccess)
-            return fail_device(e, "pivot launch");
+    uint32_t *counts = reinterpret_cast<uint32_t *>(take(2));  // [0] list A, [1] list B, [2] leaves, [3] overflow
+    SegList LA{take(capS), take(capS), take(capS), counts + 0};
+    SegList LB{take(capS), take(capS), take(capS), counts + 1};
+    QsCtl C;
+    C.piv = take(capS);
+    C.leaf_count = counts + 2;
+    C.overflow = counts + 3;
+    C.leaf_start = take(capL);
+    C.leaf_len = take(capL);
+    C.report = take(2);
+    C.cap_segs = (uint32_t)capS;
+    C.cap_leaves = (uint32_t)capL;
+    C.leaf_cap = cap;
+    BatchState B;
+    B.pivot = C.piv;
+    B.lo = take(capS);
+    B.hi = take(capS);
+    B.split = take(capS);
+    B.first = take(capS + 1);
+    B.vout = take(items);
+    B.g = reinterpret_cast<uint32_t *>(take((capS + 1) / 2 + 1));
+    B.imap = reinterpret_cast<uint32_t *>(take((items + 1) / 2));
+    B.ctl = take(8);
+    B.num = (uint32_t)capS;
+
+    const uint32_t grid_s = (uint32_t)((capS + 255) / 256);
+    hipLaunchKernelGGL(k_qinit, dim3(1), dim3(64), 0, st, LA, C, (uint64_t)n);
+    (*launches)++;
+    if (n <= cap) {
+        // the whole array is one leaf
+        QLeafArgs a{base, LA.start, LA.len, nullptr, 1u, nullptr, nullptr, nullptr};
+        if ((e = launch_qleaf(dtype, a, st)) != hipSuccess)
+            return fail_device(e, "leaf sort launch");
         (*launches)++;
-        B.pivot = piv2_dev;
-        uint32_t lv = 0;
-        if ((rc = batched_core(base, dtype, R, B, icap, st, split_host_dev, true, launches, &lv)))
-            return rc;
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return fail_device(e, "hipStreamSynchronize");
-        levels++;
-        // children; segments whose pivot was their minimum need the <= pass
-        nxt_start.clear();
-        nxt_len.clear();
-        eq_idx.clear();
-        std::vector<uint64_t> split1(split_host, split_host + m), piv(piv_host, piv_host + m);
-        for (uint32_t k = 0; k < m; k++) {
-            const uint64_t s1 = split1[k];
-            if (s1 == ~0ull)
-                return fail_msg(SS_EDEVICE, "quicksort: unfinished partition");
-            if (s1 == 0) {
-                eq_idx.push_back(k);
-                continue;
-            }
-            add_child(seg_start[k], s1);
-            add_child(seg_start[k] + s1, seg_len[k] - s1);
-        }
-        if (!eq_idx.empty()) {
-            std::vector<uint64_t> es, el, ep;
-            for (uint64_t k : eq_idx) {
-                if (piv[k] == ~0ull) {
-                    continue;  // every key equals the largest possible key: the segment is sorted
-                }
-                es.push_back(seg_start[k]);
-                el.push_back(seg_len[k]);
-                ep.push_back(piv[k] + 1);  // key <= p  <=>  key < p + 1
-            }
-            const uint32_t m2 = (uint32_t)es.size();
-            if (m2) {
-                const uint64_t icap2 = batched_items_cap(el.data(), m2, R.tile / R.w);
-                BatchState B2;
-                if ((rc = batched_state(dev, st, m2, icap2, &B2, &bstage)))
-                    return rc;
-                if ((e = hipStreamSynchronize(st)) != hipSuccess)
-                    return fail_device(e, "hipStreamSynchronize");
-                std::memcpy(bstage, es.data(), m2 * sizeof(uint64_t));
-                std::memcpy(bstage + m2, el.data(), m2 * sizeof(uint64_t));
-                std::memcpy(w->stage, ep.data(), m2 * sizeof(uint64_t));
-                if ((e = hipMemcpyAsync(B2.start, bstage, 2 * (size_t)m2 * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                        st)) != hipSuccess ||
-                    (e = hipMemcpyAsync(piv2_dev, w->stage, m2 * sizeof(uint64_t), hipMemcpyHostToDevice, st)) !=
-                        hipSuccess)
-                    return fail_device(e, "hipMemcpyAsync");
-                B2.pivot = piv2_dev;
-                if ((rc = batched_core(base, dtype, R, B2, icap2, st, split_host_dev, true, launches, &lv)))
-                    return rc;
-                if ((e = hipStreamSynchronize(st)) != hipSuccess)
-                    return fail_device(e, "hipStreamSynchronize");
-                for (uint32_t k = 0; k < m2; k++) {
-                    const uint64_t s2 = split_host[k];
-                    if (s2 == ~0ull || s2 == 0)
-                        return fail_msg(SS_EDEVICE, "quicksort: unfinished equal-key pass");
-                    add_child(es[k] + s2, el[k] - s2);  // [start, start + s2) holds only the pivot's key
-                }
-            }
-        }
-        seg_start.swap(nxt_start);
-        seg_len.swap(nxt_len);
-        if (leaf_start.size() > max_leaves)
-            return fail_msg(SS_EDEVICE, "quicksort: leaf list overflow");
-        if (levels > 4096)
-            return fail_msg(SS_EDEVICE, "quicksort: no progress");
+        return SS_OK;
     }
-    const size_t nl = leaf_start.size();
-    if (nl) {
-        std::memcpy(w->stage, leaf_start.data(), nl * sizeof(uint64_t));
-        std::memcpy(w->stage + nl, leaf_len.data(), nl * sizeof(uint64_t));
-        if ((e = hipMemcpyAsync(leaf_dev, w->stage, 2 * nl * sizeof(uint64_t), hipMemcpyHostToDevice, st)) !=
-            hipSuccess)
-            return fail_device(e, "hipMemcpyAsync");
-        for (size_t k0 = 0; k0 < nl; k0 += 65535) {
-            const uint32_t cnt = (uint32_t)(nl - k0 < 65535 ? nl - k0 : 65535);
-            if ((e = launch_qleaf(dtype, base, leaf_dev + k0, leaf_dev + nl + k0, cnt, st)) != hipSuccess)
-                return fail_device(e, "leaf sort launch");
-            (*launches)++;
+    auto enqueue = [&](uint32_t L, uint64_t max_len) -> int {
+        const SegList &cur = (L & 1) ? LB : LA;
+        const SegList &nxt = (L & 1) ? LA : LB;
+        hipError_t e2;
+        switch (dtype) {
+        case SS_U32: e2 = launch_qprep<uint32_t>(base, cur, nxt, C, grid_s, st); break;
+        case SS_U64: e2 = launch_qprep<uint64_t>(base, cur, nxt, C, grid_s, st); break;
+        default: e2 = launch_qprep<KV>(base, cur, nxt, C, grid_s, st); break;
         }
+        if (e2 != hipSuccess)
+            return fail_device(e2, "pivot launch");
+        B.start = cur.start;
+        B.len = cur.len;
+        B.count = cur.count;
+        const int rc2 = batched_core(base, dtype, R, B, batched_levels(max_len, tile_elems), st, nullptr, launches);
+        if (rc2)
+            return rc2;
+        hipLaunchKernelGGL(k_qchildren, dim3(grid_s), dim3(256), 0, st, cur, nxt, C, (const uint64_t *)B.split);
+        QLeafArgs a{base, C.leaf_start, C.leaf_len, C.leaf_count, 0u, nxt.count, C.report + 1, W->rep_dev + 2 * L};
+        if ((e2 = launch_qleaf(dtype, a, st)) != hipSuccess)
+            return fail_device(e2, "leaf sort launch");
+        *launches += 3;
+        if ((e2 = hipEventRecord(W->ev[L & 3], st)) != hipSuccess)
+            return fail_device(e2, "hipEventRecord");
+        return SS_OK;
+    };
+    // Level L + 2 is issued once level L has completed: its segments are
+    // children of level L + 1's, whose count and longest length level L
+    // reported.
+    if ((rc = enqueue(0, n)) || (rc = enqueue(1, n)))
+        return rc;
+    uint32_t L = 0;
+    for (;;) {
+        if ((e = hipEventSynchronize(W->ev[L & 3])) != hipSuccess)
+            return fail_device(e, "hipEventSynchronize");
+        const volatile uint64_t *rep = W->rep + 2 * L;
+        const uint64_t next_segs = rep[0], next_max = rep[1];
+        if (next_segs == 0)
+            break;  // level L + 1 (already issued) has nothing to do
+        if (L + 2 >= kMaxQsLevels)
+            return fail_msg(SS_EDEVICE, "quicksort: no progress");
+        if ((rc = enqueue(L + 2, next_max)))
+            return rc;
+        L++;
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return fail_device(e, "hipStreamSynchronize");
-    *levels_out = levels;
+    uint32_t ovf = 0;
+    if ((e = hipMemcpy(&ovf, C.overflow, sizeof(ovf), hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail_device(e, "hipMemcpy");
+    if (ovf)
+        return fail_msg(SS_EDEVICE, ovf & 2u ? "quicksort: unfinished partition" : "quicksort: segment list overflow");
+    *levels_out = L + 1;
     return SS_OK;
 }
 
@@ -424,8 +610,6 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the batched Smoothed Striding partition");
     if (R.engine != SS_ENGINE_REGS)
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the register engine");
-    if (!p || !p->max_levels)
-        R.levels = 6;
     if ((rc = check_lines(n, R)))
         return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -568,10 +752,10 @@ extern "C" int ss_sort_segments(void *d_base, const uint64_t *h_starts, const ui
     uint64_t *ds = nullptr, *dl = nullptr;
     if ((rc = upload_segments(dev, st, h_starts, h_lens, num, &w, &ds, &dl)))
         return rc;
-    for (size_t k0 = 0; k0 < num; k0 += 65535) {
-        const uint32_t cnt = (uint32_t)(num - k0 < 65535 ? num - k0 : 65535);
-        if ((e = launch_qleaf(dtype, (char *)d_base, ds + k0, dl + k0, cnt, st)) != hipSuccess)
-            return fail_device(e, "segment sort launch");
-    }
+    if (num > 0xffffffffull)
+        return fail_msg(SS_EINVAL, "too many segments");
+    QLeafArgs a{(char *)d_base, ds, dl, nullptr, (uint32_t)num, nullptr, nullptr, nullptr};
+    if ((e = launch_qleaf(dtype, a, st)) != hipSuccess)
+        return fail_device(e, "segment sort launch");
     return SS_OK;
 }
