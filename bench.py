@@ -273,17 +273,29 @@ def run_batched(args):
     d_split = torch.empty(len(lens), dtype=torch.int64, device=dev)
     buf = torch.empty_like(pristine)
     reps = max(1, min(args.steps, 5))
-    # batched: one call over all arrays
-    bt = []
-    for r in range(reps + 1):
-        buf.copy_(pristine)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ss.partition_batched(buf, offs, d_piv, d_split)
-        torch.cuda.synchronize()
-        if r:
-            bt.append(time.perf_counter() - t0)
-    splits_b = d_split.cpu().numpy().copy()
+
+    def timed(graph):
+        ts = []
+        for r in range(reps + 1):   # with graph=True the first call captures the graph
+            buf.copy_(pristine)
+            d_split.fill_(-1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ss.partition_batched(buf, offs, d_piv, d_split, graph=graph)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        return min(ts), d_split.cpu().numpy().copy()
+
+    # batched, one call over all arrays: default geometry, then the autotuned size classes,
+    # each with eager launches and with the level chain replayed from a captured HIP graph
+    ss.set_batched_tuning("u64", None)
+    t_default, splits_b = timed(False)
+    tune_t0 = time.perf_counter()
+    tuning = ss.autotune_batched("u64")
+    tune_s = time.perf_counter() - tune_t0
+    te, splits_e = timed(False)
+    tg, splits_g = timed(True)
     # per-array: one asynchronous call per array on one stream, an event after each
     st = torch.cuda.current_stream()
     pt, lat = [], None
@@ -303,17 +315,22 @@ def run_batched(args):
         lat = np.array([ev0.elapsed_time(e) for e in evs])
     splits_p = d_split.cpu().numpy()
     bytes_ = 2 * 8 * total
-    tb = min(bt)
+    tb = min(te, tg)
     tp = min(pt)
     return {"metric": "batched partition GB/s and p99 latency, 20000 uint64 arrays (log-normal, median 2^14)",
             "value": round(bytes_ / tb / 1e9, 1), "unit": "GB/s",
             "batched": {"ms": round(tb * 1e3, 3), "GBps": round(bytes_ / tb / 1e9, 1),
                         "elements_per_s": round(total / tb, 1), "p50_ms": round(tb * 1e3, 3),
-                        "p99_ms": round(tb * 1e3, 3)},
+                        "p99_ms": round(tb * 1e3, 3), "eager_ms": round(te * 1e3, 3), "graph_ms": round(tg * 1e3, 3),
+                        "launch": "graph" if tg <= te else "eager", "default_geometry_ms": round(t_default * 1e3, 3)},
+            "autotune": {"seconds": round(tune_s, 2),
+                         "classes": [{k: c[k] for k in ("max_len", "b", "group_bytes")} for c in tuning["classes"]]},
             "per_array": {"ms": round(tp * 1e3, 3), "GBps": round(bytes_ / tp / 1e9, 1),
                           "elements_per_s": round(total / tp, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                           "p99_ms": round(float(np.percentile(lat, 99)), 3)},
-            "speedup": round(tp / tb, 2), "splits_agree": bool(np.array_equal(splits_b, splits_p)),
+            "speedup": round(tp / tb, 2),
+            "splits_agree": bool(np.array_equal(splits_b, splits_p) and np.array_equal(splits_b, splits_g)
+                                 and np.array_equal(splits_b, splits_e)),
             "config": {"workload": "batched_u64_20000", "arrays": len(lens), "elements": total,
                        "pivot": "u-quantile of the key distribution, u ~ U[0.05, 0.95]"}}
 

@@ -90,6 +90,8 @@ enum ss_status {
                                   the call's stream; reported in ss_stats (synchronizes). */
 #define SS_FLAG_STREAM 4u      /* register engines: non-temporal (streaming) loads and stores */
 #define SS_FLAG_XCD_ORDER 8u   /* register engines: consecutive groups on the same XCD */
+#define SS_FLAG_GRAPH 16u      /* batched calls: issue the level chain as a captured HIP graph, cached per
+                                  (stream, buffers, batch shape) and replayed when they recur */
 
 /* Tuning parameters; a zero field means "choose automatically". */
 typedef struct ss_params {
@@ -176,15 +178,20 @@ int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params *p, void *
                     ss_stats *stats);
 
 /* Partition `num` independent arrays stored back to back in d_base (Section 2
- * problem applied to each): array k is d_base[h_offsets[k], h_offsets[k+1])
- * in elements, with its own pivot d_pivots[k] (device); its split, relative
- * to its own start, is written to d_splits[k] (device).  h_offsets is a host
- * array of num+1 non-decreasing element offsets.  All arrays are processed
- * by one persistent kernel per recursion level, arrays that fit one LDS tile
- * as a single group.  stats may be NULL.  Asynchronous unless stats != NULL;
- * d_splits[k] = UINT64_MAX marks an array whose recursion did not finish in
- * the device budget (then SS_EINCOMPLETE is returned by a synchronizing
- * call only if it cannot finish it from the host, which does not happen). */
+ * problem applied to each, Section 4 algorithm): array k is
+ * d_base[h_offsets[k], h_offsets[k+1]) in elements, with its own pivot
+ * d_pivots[k] (device); its split, relative to its own start, is written to
+ * d_splits[k] (device).  h_offsets is a host array of num+1 non-decreasing
+ * element offsets.  All arrays are processed by one persistent kernel per
+ * recursion level; an array that fits one group finishes at the first level.
+ * The number of levels is planned from the longest array, and an array still
+ * open after them is finished by a single-workgroup cleanup, so a call is a
+ * fixed launch sequence (with SS_FLAG_GRAPH, replayed from a cached HIP
+ * graph).  Lines and groups follow the installed size-class tuning
+ * (ss_autotune_batched / ss_set_batched_tuning) unless p sets b or
+ * tile_bytes.  The call waits for earlier work on `stream` (its host staging
+ * buffer is reused), then returns without waiting unless stats != NULL.
+ * stats may be NULL. */
 int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, int dtype,
                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                          void *stream, ss_stats *stats);
@@ -199,6 +206,78 @@ int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, in
 int ss_partition_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
                           const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p, void *stream,
                           ss_stats *stats);
+
+/* Size classes of the batched calls: arrays of length in
+ * (max_len[c-1], max_len[c]] use lines of b[c] elements and groups of
+ * group_bytes[c] bytes (s = group_bytes / (b * element size) lines); the
+ * last class in use takes every longer array.  group_bytes <= 131072. */
+#define SS_MAX_CLASSES 8
+typedef struct ss_batched_tuning {
+    uint32_t nclass;                      /* classes in use, 1..SS_MAX_CLASSES */
+    uint32_t b[SS_MAX_CLASSES];           /* elements per line (b * element size: 64..4096 bytes) */
+    uint32_t group_bytes[SS_MAX_CLASSES]; /* bytes per group */
+    uint64_t max_len[SS_MAX_CLASSES];     /* upper length bound of each class */
+    float ms[SS_MAX_CLASSES];             /* ss_autotune_batched: best time of the class's tuning batch */
+} ss_batched_tuning;
+
+/* Autotune the batched partition for dtype on the current device: for each
+ * of seven length classes (up to 2^10, 2^12, ..., 2^20 elements, and longer)
+ * a synthetic batch of about 2^24 elements (log-uniform lengths in the class,
+ * uniform keys, pivots at uniform quantiles) is partitioned with every
+ * candidate line size (128..1024 bytes) and group size (32..128 KiB), timed
+ * with HIP events; the fastest candidate of each class is installed for
+ * later batched calls of this dtype on this device and returned in *out
+ * (nullable).  Allocates and frees its own device scratch (a few hundred
+ * MiB); synchronizes `stream`. */
+int ss_autotune_batched(int dtype, void *stream, ss_batched_tuning *out);
+
+/* Install a size-class table (e.g. one saved from ss_autotune_batched) for
+ * dtype on the current device; t == NULL restores the single default class
+ * (512-byte lines, 128 KiB groups).  SS_EINVAL for an invalid table. */
+int ss_set_batched_tuning(int dtype, const ss_batched_tuning *t);
+
+/* The table in use for dtype on the current device (the default class when
+ * none is installed). */
+int ss_get_batched_tuning(int dtype, ss_batched_tuning *t);
+
+/* Device-resident serving engine: continuous batching of partition and sort
+ * jobs over one caller-owned array d_base[0, capacity) of dtype (the job
+ * records live there; the caller places each job in a disjoint range).  All
+ * job state -- pending segments, leaves, per-job outstanding counters --
+ * stays on the device; a tick is a fixed launch sequence (submitted jobs
+ * appended; pivots; one batched Smoothed Striding partition of every pending
+ * segment of every job, Section 4; children and leaves of sort jobs as in the
+ * quicksort, Section 5.2; leaf sorts) issued on `stream` without waiting.
+ * Finished jobs raise a flag in mapped host memory, read with
+ * ss_server_done once the tick that finished them has completed
+ * (ss_server_wait).  max_jobs slots; max_segments bounds the segments
+ * pending at once (a sort job of n records can hold n / (leaf capacity + 1)
+ * + 1 of them; the caller's admission must keep the sum within it -- see
+ * ss_server_job_aux_bytes).  The engine allocates its device state at
+ * creation and nothing per tick.  Calls on one engine must not overlap. */
+typedef struct ss_server ss_server;
+int ss_server_create(void *d_base, size_t capacity, int dtype, uint32_t max_jobs, uint32_t max_segments,
+                     void *stream, ss_server **out);
+int ss_server_destroy(ss_server *s);
+/* Queue a job for the next tick: kind 0 partitions d_base[start, start+len)
+ * by key < pivot, kind 1 sorts it ascending by key.  The slot must be free
+ * (its previous job reported done). */
+int ss_server_submit(ss_server *s, uint32_t slot, uint64_t start, uint64_t len, int kind, uint64_t pivot);
+/* Issue one tick; max_len bounds the longest pending segment (the longest
+ * active job will do) and sets the number of partition levels.  At most four
+ * ticks are kept in flight (the call waits for the oldest beyond that). */
+int ss_server_tick(ss_server *s, uint64_t max_len);
+/* Wait until at most `in_flight` issued ticks are still running. */
+int ss_server_wait(ss_server *s, uint32_t in_flight);
+/* 1 if the job in `slot` finished in a completed tick (a partition job's split,
+ * relative to its start, in *split if non-NULL), 0 if not, < 0 on error. */
+int ss_server_done(ss_server *s, uint32_t slot, uint64_t *split);
+/* Overflow flags of the device lists after synchronizing the stream (0: every
+ * capacity held; 1: a list was full; 2: an unfinished partition). */
+int ss_server_status(ss_server *s, uint32_t *flags);
+/* Device bytes of list, leaf and item state a job reserves in an engine:
+ * what admission adds to the job's input bytes. */
+size_t ss_server_job_aux_bytes(int dtype, int kind, uint64_t len);
 
 /* The quicksort's median-of-3 pivot of every segment (Section 5.2 quicksort;
  * the median of the keys at offsets 0, len/2 and len-1): d_pivots[k]

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(_SO)
 SS_U32, SS_U64, SS_KV16 = 1, 2, 3
 SMOOTHED, STRIDED, LOWSPACE = 0, 1, 2
 ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE}
-FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER = 1, 2, 4, 8
+FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH = 1, 2, 4, 8, 16
 MAX_LEVELS = 32
 STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",
           -5: "SS_EINCOMPLETE"}
@@ -39,6 +39,32 @@ class Params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("b", ctypes.c_uint32), ("tile_bytes", ctypes.c_uint32),
                 ("max_levels", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("engine", ctypes.c_uint32)]
+
+
+MAX_CLASSES = 8
+
+
+class Tuning(ctypes.Structure):
+    """ss_batched_tuning: size classes of the batched calls."""
+    _fields_ = [("nclass", ctypes.c_uint32), ("b", ctypes.c_uint32 * MAX_CLASSES),
+                ("group_bytes", ctypes.c_uint32 * MAX_CLASSES), ("max_len", ctypes.c_uint64 * MAX_CLASSES),
+                ("ms", ctypes.c_float * MAX_CLASSES)]
+
+    def as_dict(self) -> dict:
+        n = self.nclass
+        return {"classes": [{"max_len": int(self.max_len[c]), "b": int(self.b[c]),
+                             "group_bytes": int(self.group_bytes[c]), "ms": round(float(self.ms[c]), 4)}
+                            for c in range(n)]}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tuning":
+        t = cls()
+        cl = d["classes"]
+        t.nclass = len(cl)
+        for c, x in enumerate(cl):
+            t.b[c], t.group_bytes[c], t.max_len[c] = x["b"], x["group_bytes"], x["max_len"]
+            t.ms[c] = x.get("ms", 0.0)
+        return t
 
 
 class Stats(ctypes.Structure):
@@ -75,6 +101,19 @@ _lib.ss_partition_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, ctype
                                        ctypes.POINTER(Stats)]
 _lib.ss_median3_pivots.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, _vp]
 _lib.ss_sort_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp]
+_lib.ss_autotune_batched.argtypes = [_int, _vp, ctypes.POINTER(Tuning)]
+_lib.ss_set_batched_tuning.argtypes = [_int, ctypes.POINTER(Tuning)]
+_lib.ss_get_batched_tuning.argtypes = [_int, ctypes.POINTER(Tuning)]
+_u32 = ctypes.c_uint32
+_lib.ss_server_create.argtypes = [_vp, _sz, _int, _u32, _u32, _vp, ctypes.POINTER(_vp)]
+_lib.ss_server_destroy.argtypes = [_vp]
+_lib.ss_server_submit.argtypes = [_vp, _u32, _u64, _u64, _int, _u64]
+_lib.ss_server_tick.argtypes = [_vp, _u64]
+_lib.ss_server_wait.argtypes = [_vp, _u32]
+_lib.ss_server_done.argtypes = [_vp, _u32, ctypes.POINTER(_u64)]
+_lib.ss_server_status.argtypes = [_vp, ctypes.POINTER(_u32)]
+_lib.ss_server_job_aux_bytes.argtypes = [_int, _int, _u64]
+_lib.ss_server_job_aux_bytes.restype = _sz
 _lib.ss_sort_segment_cap.argtypes = [_int]
 _lib.ss_sort_segment_cap.restype = _sz
 _lib.ss_aux_bytes.argtypes = [_sz, _int, _int]
@@ -138,10 +177,10 @@ ENGINES = {"auto": 0, "lds": 1, "regs": 2, "regs2": 3}
 
 
 def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False,
-                engine="auto", stream=False, xcd_order=False) -> Params:
+                engine="auto", stream=False, xcd_order=False, graph=False) -> Params:
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0) | (FLAG_STREAM if stream else 0) \
-        | (FLAG_XCD_ORDER if xcd_order else 0)
+        | (FLAG_XCD_ORDER if xcd_order else 0) | (FLAG_GRAPH if graph else 0)
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
     return Params(a, b, tile_bytes, max_levels, seed, flags, e)
 
@@ -200,6 +239,33 @@ def partition_batched(base, offsets, pivots, splits, *, stats: bool = False, str
     return st.as_dict() if stats else None
 
 
+def autotune_batched(dtype, stream=None) -> dict:
+    """Time every candidate line and group size per length class on synthetic
+    batches and install the fastest for later batched calls of dtype."""
+    t = Tuning()
+    _check(_lib.ss_autotune_batched(_dtype_code(dtype), _stream(stream), ctypes.byref(t)), "ss_autotune_batched")
+    return t.as_dict()
+
+
+def set_batched_tuning(dtype, table) -> None:
+    """Install a table (a dict as returned by autotune_batched), or None for the default."""
+    t = Tuning.from_dict(table) if table is not None else None
+    _check(_lib.ss_set_batched_tuning(_dtype_code(dtype), ctypes.byref(t) if t is not None else None),
+           "ss_set_batched_tuning")
+
+
+def get_batched_tuning(dtype) -> dict:
+    t = Tuning()
+    _check(_lib.ss_get_batched_tuning(_dtype_code(dtype), ctypes.byref(t)), "ss_get_batched_tuning")
+    return t.as_dict()
+
+
+def _dtype_code(dtype) -> int:
+    if isinstance(dtype, int):
+        return dtype
+    return {"u32": SS_U32, "u64": SS_U64, "kv": SS_KV16, "kv16": SS_KV16}[dtype]
+
+
 def _u64_host(x):
     import numpy as np
     a = np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
@@ -240,6 +306,55 @@ def sort_segments(base, starts, lens, *, stream=None):
     s_arr, s_ptr = _u64_host(starts)
     l_arr, l_ptr = _u64_host(lens)
     _check(_lib.ss_sort_segments(ptr, s_ptr, l_ptr, len(s_arr), dt, _stream(stream)), "ss_sort_segments")
+
+
+class ServerEngine:
+    """The device-resident serving engine (ss_server_*) over one CUDA tensor."""
+
+    def __init__(self, base, max_jobs: int, max_segments: int, stream=None):
+        ptr, n, dt = _array(base)
+        self.dtype = dt
+        self._h = _vp()
+        _check(_lib.ss_server_create(ptr, n, dt, max_jobs, max_segments, _stream(stream), ctypes.byref(self._h)),
+               "ss_server_create")
+
+    def submit(self, slot: int, start: int, length: int, kind: int, pivot: int = 0) -> None:
+        _check(_lib.ss_server_submit(self._h, slot, start, length, kind, pivot & ((1 << 64) - 1)),
+               "ss_server_submit")
+
+    def tick(self, max_len: int) -> None:
+        _check(_lib.ss_server_tick(self._h, max_len), "ss_server_tick")
+
+    def wait(self, in_flight: int = 0) -> None:
+        _check(_lib.ss_server_wait(self._h, in_flight), "ss_server_wait")
+
+    def done(self, slot: int):
+        """(finished, split) for the job in slot; split only for partition jobs."""
+        sp = _u64(0)
+        rc = _lib.ss_server_done(self._h, slot, ctypes.byref(sp))
+        if rc < 0:
+            _check(rc, "ss_server_done")
+        return bool(rc), int(sp.value)
+
+    def status(self) -> int:
+        f = _u32(0)
+        _check(_lib.ss_server_status(self._h, ctypes.byref(f)), "ss_server_status")
+        return int(f.value)
+
+    def close(self) -> None:
+        if self._h:
+            _lib.ss_server_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_job_aux_bytes(dtype: int, kind: int, length: int) -> int:
+    return _lib.ss_server_job_aux_bytes(dtype, kind, length)
 
 
 def sort_segment_cap(dtype: int) -> int:

@@ -161,7 +161,7 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r)
         q = *p;
     if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE)
         return fail_msg(SS_EINVAL, "unknown algo");
-    if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER))
+    if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH))
         return fail_msg(SS_EINVAL, "unknown flags");
     if (q.engine > SS_ENGINE_REGS2)
         return fail_msg(SS_EINVAL, "unknown engine");

@@ -36,6 +36,8 @@
 #include "ss_levelctx.h"
 
 #include <algorithm>
+#include <cmath>
+#include <tuple>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -45,9 +47,9 @@ namespace ss {
 
 struct BatchGeom {
     char *base;
-    uint32_t w, log2b, s_max;
     uint64_t seed;
     uint32_t level;
+    BatchClasses C;
 };
 
 __device__ __forceinline__ uint32_t bnum(const BatchState &B)
@@ -58,49 +60,54 @@ __device__ __forceinline__ uint32_t bnum(const BatchState &B)
 __device__ __forceinline__ uint32_t plan_groups(const BatchState &B, const BatchGeom &Gm, uint32_t k, uint64_t lo,
                                                 uint64_t hi)
 {
-    return plan_geo(lo - B.start[k], hi - B.start[k], Gm.log2b, Gm.s_max).g;
+    const uint32_t c = B.cls[k];
+    return plan_geo(lo - B.start[k], hi - B.start[k], Gm.C.log2b[c], Gm.C.s_max[c]).g;
 }
 
 // First level: every array's region is the whole array.
 __global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
 {
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= bnum(B))
-        return;
-    const uint64_t s = B.start[k], l = B.len[k];
-    B.lo[k] = s;
-    B.hi[k] = s + l;
-    B.split[k] = l ? ~0ull : s;
-    B.g[k] = l ? plan_groups(B, Gm, k, s, s + l) : 0u;
+    const uint32_t num = bnum(B);
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < num; k += gridDim.x * 256) {
+        const uint64_t s = B.start[k], l = B.len[k];
+        uint32_t c = 0;
+        while (c + 1 < Gm.C.n && l > Gm.C.max_len[c])
+            c++;
+        B.cls[k] = (uint8_t)c;
+        B.lo[k] = s;
+        B.hi[k] = s + l;
+        B.split[k] = l ? ~0ull : s;
+        B.g[k] = l ? plan_groups(B, Gm, k, s, s + l) : 0u;
+    }
 }
 
 // Later levels: fold the previous level's splitting positions of array k
 // (one wavefront per array), then plan the next level.
 __global__ void __launch_bounds__(256) k_bstep(BatchState B, BatchGeom Gm)
 {
-    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= bnum(B))
-        return;
-    const uint32_t g = B.g[k];
-    if (g == 0)
-        return;
-    const uint64_t f = B.first[k];
-    uint64_t mn = ~0ull, mx = 0;
-    for (uint32_t i = threadIdx.x & 63; i < g; i += 64) {
-        const uint64_t v = B.vout[f + i];
-        mn = v < mn ? v : mn;
-        mx = v > mx ? v : mx;
-    }
-    mn = wave_min(mn);
-    mx = wave_max(mx);
-    if ((threadIdx.x & 63) == 0) {
-        if (g == 1 || !(mn < mx)) {
-            B.split[k] = mn;
-            B.g[k] = 0;
-        } else {
-            B.lo[k] = mn;
-            B.hi[k] = mx;
-            B.g[k] = plan_groups(B, Gm, k, mn, mx);
+    const uint32_t num = bnum(B);
+    for (uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6); k < num; k += gridDim.x * 4) {
+        const uint32_t g = B.g[k];
+        if (g == 0)
+            continue;
+        const uint64_t f = B.first[k];
+        uint64_t mn = ~0ull, mx = 0;
+        for (uint32_t i = threadIdx.x & 63; i < g; i += 64) {
+            const uint64_t v = B.vout[f + i];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        if ((threadIdx.x & 63) == 0) {
+            if (g == 1 || !(mn < mx)) {
+                B.split[k] = mn;
+                B.g[k] = 0;
+            } else {
+                B.lo[k] = mn;
+                B.hi[k] = mx;
+                B.g[k] = plan_groups(B, Gm, k, mn, mx);
+            }
         }
     }
 }
@@ -176,13 +183,13 @@ __global__ void __launch_bounds__(kScanNT) k_bscan(BatchState B)
 
 __global__ void __launch_bounds__(256) k_bfill(BatchState B)
 {
-    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= bnum(B))
-        return;
-    const uint64_t f = B.first[k];
-    const uint32_t g = B.g[k];
-    for (uint32_t i = threadIdx.x & 63; i < g; i += 64)
-        B.imap[f + i] = k;
+    const uint32_t num = bnum(B);
+    for (uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6); k < num; k += gridDim.x * 4) {
+        const uint64_t f = B.first[k];
+        const uint32_t g = B.g[k];
+        for (uint32_t i = threadIdx.x & 63; i < g; i += 64)
+            B.imap[f + i] = k;
+    }
 }
 
 template <typename T, int NT, int NV>
@@ -200,15 +207,16 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
         const uint32_t k = B.imap[t];
         const uint32_t i = (uint32_t)(t - B.first[k]);
         const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
-        const Geo G = plan_geo(lo - start, hi - start, Gm.log2b, Gm.s_max);
+        const uint32_t cl = B.cls[k], log2b = Gm.C.log2b[cl];
+        const Geo G = plan_geo(lo - start, hi - start, log2b, Gm.C.s_max[cl]);
         Ctx x;
         x.g = G.g;
         x.s = G.s;
         x.fp = G.fp;
         x.real_end = (uint64_t)G.fp + (hi - lo);
         x.A0 = Gm.base + (lo - G.fp) * W;  // line grid counted from the array's first element
-        x.log2b = Gm.log2b;
-        x.vpl_log2 = Gm.log2b + Ctx::LOG2W - 4;
+        x.log2b = log2b;
+        x.vpl_log2 = log2b + Ctx::LOG2W - 4;
         x.nvec = G.s << x.vpl_log2;
         x.pivot = B.pivot[k];
         x.xoff = xoff;
@@ -232,11 +240,11 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
         }
         if (tid == 0) {
             uint64_t vi;
-            if (c >= (G.s << Gm.log2b)) {
+            if (c >= (G.s << log2b)) {
                 vi = hi;
             } else {
                 const uint64_t vp =
-                    ((uint64_t)x.line_of(c >> Gm.log2b, i) << Gm.log2b) + (c & ((1u << Gm.log2b) - 1));
+                    ((uint64_t)x.line_of(c >> log2b, i) << log2b) + (c & ((1u << log2b) - 1));
                 vi = vp >= x.real_end ? hi : lo + (vp - G.fp);
             }
             B.vout[t] = vi;
@@ -264,11 +272,11 @@ __global__ void __launch_bounds__(1024) k_bcleanup(BatchState B, BatchGeom Gm)
 
 __global__ void __launch_bounds__(256) k_bfinish(BatchState B, uint64_t *d_splits)
 {
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= bnum(B))
-        return;
-    const uint64_t s = B.split[k];
-    d_splits[k] = s == ~0ull ? ~0ull : s - B.start[k];
+    const uint32_t num = bnum(B);
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < num; k += gridDim.x * 256) {
+        const uint64_t s = B.split[k];
+        d_splits[k] = s == ~0ull ? ~0ull : s - B.start[k];
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -343,8 +351,19 @@ uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems)
 // device memory (B.start, B.len): `levels` persistent level launches, then
 // the cleanup of any array still open, then (if d_splits) the splits
 // relative to each start.  A fixed chain of launches with no host decision.
-int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint32_t levels, hipStream_t st,
-                 uint64_t *d_splits, uint32_t *launches)
+BatchClasses batched_default_classes(const Resolved &R)
+{
+    BatchClasses C;
+    std::memset(&C, 0, sizeof(C));
+    C.n = 1;
+    C.max_len[0] = ~0ull;
+    C.log2b[0] = R.log2b;
+    C.s_max[0] = (uint32_t)(R.tile / ((uint64_t)R.b * R.w));
+    return C;
+}
+
+int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B, uint32_t levels,
+                 hipStream_t st, uint64_t *d_splits, uint32_t *launches)
 {
     hipError_t e;
     int dev = 0;
@@ -362,14 +381,17 @@ int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint32
     if ((rc = occupancy(dev, V->fn(), V->nt, &occ)))
         return rc;
     const uint32_t P = (uint32_t)(occ * cus);
+    for (uint32_t c = 0; c < BC.n; c++)
+        if (((uint64_t)BC.s_max[c] << BC.log2b[c]) * R.w > tile || !BC.s_max[c])
+            return fail_msg(SS_EINVAL, "size class geometry exceeds the batched kernel's tile");
     BatchGeom Gm;
     Gm.base = base;
-    Gm.w = R.w;
-    Gm.log2b = R.log2b;
-    Gm.s_max = (uint32_t)(tile / ((uint64_t)R.b * R.w));
     Gm.seed = R.seed;
     Gm.level = 0;
-    const uint32_t nb256 = (B.num + 255) / 256, nb4 = (B.num + 3) / 4;
+    Gm.C = BC;
+    // per-array kernels loop over the arrays; their grids are capped
+    const uint32_t nb256 = std::min<uint32_t>((B.num + 255) / 256, 1024u),
+                   nb4 = std::min<uint32_t>((B.num + 3) / 4, 2048u);
     if (levels < 1)
         levels = 1;
     for (uint32_t level = 0; level < levels; level++) {
@@ -406,12 +428,15 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
 {
     std::lock_guard<std::mutex> lk(g_b_mu);
     BatchWork &w = g_b[std::make_pair(dev, stream)];
-    const size_t words = 8 + (size_t)num * 6 + (num + 1) + items_cap + (items_cap + 1) / 2 + (size_t)(num + 1) / 2 + 16;
+    const size_t words = 8 + (size_t)num * 6 + (num + 1) + items_cap + (items_cap + 1) / 2 + (size_t)(num + 1) / 2 +
+                         (size_t)num / 8 + 1 + 16;
     const size_t bytes = words * sizeof(uint64_t);
     hipError_t e;
     if (w.dev_bytes < bytes) {
-        if (w.dev)
+        if (w.dev) {
+            batched_graphs_forget(w.dev);
             (void)hipFree(w.dev);
+        }
         w.dev = nullptr;
         w.dev_bytes = 0;
         if ((e = hipMalloc((void **)&w.dev, bytes)) != hipSuccess) {
@@ -452,6 +477,8 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
     B->g = reinterpret_cast<uint32_t *>(p);
     p += (num + 1) / 2 + 1;
     B->imap = reinterpret_cast<uint32_t *>(p);
+    p += (items_cap + 1) / 2;
+    B->cls = reinterpret_cast<uint8_t *>(p);
     B->count = nullptr;
     B->num = num;
     *host_stage = w.host;
@@ -464,6 +491,114 @@ uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_ele
     for (uint32_t k = 0; k < num; k++)
         cap += lens[k] / tile_elems + 3;
     return cap;
+}
+
+// ------------------------------------------------------------ graph replay
+
+// The level chain of a batched call is a fixed sequence of kernel launches
+// whose arguments depend only on the buffers and the batch shape, so it is
+// captured once into a HIP graph (on a private stream; the legacy default
+// stream cannot be captured) and replayed with one hipGraphLaunch whenever
+// the same (stream, buffers, shape) recurs.  The graph holds kernel nodes
+// only; the descriptor upload stays outside it.
+namespace {
+
+struct GraphKey {
+    int dev;
+    void *stream;
+    const void *base, *pivots, *splits, *state;
+    int dtype;
+    uint32_t num, levels, tile, log2b;
+    uint64_t items_cap, seed;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(dev, stream, base, pivots, splits, state, dtype, num, levels, tile, log2b, items_cap, seed) <
+               std::tie(o.dev, o.stream, o.base, o.pivots, o.splits, o.state, o.dtype, o.num, o.levels, o.tile,
+                        o.log2b, o.items_cap, o.seed);
+    }
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint32_t launches = 0;
+    uint64_t last_use = 0;
+};
+
+std::mutex g_gr_mu;
+std::map<GraphKey, GraphEntry> g_graphs;
+std::map<int, hipStream_t> g_capture_stream;
+uint64_t g_graph_clock = 0;
+constexpr size_t kMaxGraphs = 64;
+
+}  // namespace
+
+int batched_graph(int dev, char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B,
+                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches)
+{
+    std::lock_guard<std::mutex> lk(g_gr_mu);
+    GraphKey key{dev, (void *)st, base, B.pivot, d_splits, B.ctl, dtype, B.num, levels, R.tile, 0u,
+                 items_cap, R.seed};
+    // the class table is baked into the kernel arguments: fold it into the key
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char *cb = reinterpret_cast<const unsigned char *>(&BC);
+    for (size_t j = 0; j < sizeof(BC); j++)
+        h = (h ^ cb[j]) * 1099511628211ull;
+    key.log2b = (uint32_t)(h ^ (h >> 32));
+    key.seed ^= h;
+    hipError_t e;
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        hipStream_t &cs = g_capture_stream[dev];
+        if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+            return fail_device(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return fail_device(e, "hipStreamBeginCapture");
+        uint32_t n_launch = 0;
+        const int rc = batched_core(base, dtype, R, BC, B, levels, cs, d_splits, &n_launch);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (rc) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail_device(e, "hipStreamEndCapture");
+        GraphEntry ge;
+        ge.launches = n_launch;
+        e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail_device(e, "hipGraphInstantiate");
+        if (g_graphs.size() >= kMaxGraphs) {
+            auto old = g_graphs.begin();
+            for (auto j = g_graphs.begin(); j != g_graphs.end(); ++j)
+                if (j->second.last_use < old->second.last_use)
+                    old = j;
+            (void)hipGraphExecDestroy(old->second.exec);
+            g_graphs.erase(old);
+        }
+        it = g_graphs.emplace(key, ge).first;
+    }
+    it->second.last_use = ++g_graph_clock;
+    if ((e = hipGraphLaunch(it->second.exec, st)) != hipSuccess)
+        return fail_device(e, "hipGraphLaunch");
+    *launches += it->second.launches;
+    return SS_OK;
+}
+
+// Drop cached graphs that refer to a batched workspace about to be freed.
+void batched_graphs_forget(const void *state)
+{
+    std::lock_guard<std::mutex> lk(g_gr_mu);
+    for (auto j = g_graphs.begin(); j != g_graphs.end();) {
+        if (j->first.state == state) {
+            (void)hipGraphExecDestroy(j->second.exec);
+            j = g_graphs.erase(j);
+        } else {
+            ++j;
+        }
+    }
 }
 
 // Batched partition of segments [starts[k], starts[k] + lens[k]) of d_base
@@ -482,19 +617,34 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
     if (R.engine != SS_ENGINE_REGS)
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses the register engine");
-    uint64_t max_len = 0;
-    for (size_t k = 0; k < num; k++) {
-        if ((rc = check_lines(lens[k], R)))
-            return rc;
-        max_len = lens[k] > max_len ? lens[k] : max_len;
-    }
-    const uint32_t levels = p && p->max_levels ? R.levels : batched_levels(max_len, R.tile / R.w);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
         return fail_device(e, "hipGetDevice");
-    const uint64_t items_cap = batched_items_cap(lens, (uint32_t)num, R.tile / R.w);
+    // size classes: the installed tuning unless the call fixes the geometry
+    BatchClasses BC = batched_default_classes(R);
+    if (!(p && (p->b || p->tile_bytes)))
+        batched_installed_classes(dev, dtype, R, &BC);
+    // Items (groups) per array at any level: at most len / (group elements) + 3.
+    uint64_t max_len[kMaxClasses] = {0};
+    uint64_t items_cap = 64;
+    for (size_t k = 0; k < num; k++) {
+        if ((rc = check_lines(lens[k], R)))
+            return rc;
+        uint32_t c = 0;
+        while (c + 1 < BC.n && lens[k] > BC.max_len[c])
+            c++;
+        max_len[c] = lens[k] > max_len[c] ? lens[k] : max_len[c];
+        items_cap += lens[k] / ((uint64_t)BC.s_max[c] << BC.log2b[c]) + 3;
+    }
+    uint32_t levels = 1;
+    for (uint32_t c = 0; c < BC.n; c++) {
+        const uint32_t lv = batched_levels(max_len[c], (uint64_t)BC.s_max[c] << BC.log2b[c]);
+        levels = lv > levels ? lv : levels;
+    }
+    if (p && p->max_levels)
+        levels = R.levels;
     BatchState B;
     uint64_t *stage = nullptr;
     if ((rc = batched_state(dev, stream, (uint32_t)num, items_cap, &B, &stage)))
@@ -516,7 +666,10 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
             return fail_msg(SS_EDEVICE, "hipEventCreate");
         (void)hipEventRecord(t0, st);
     }
-    rc = batched_core((char *)d_base, dtype, R, B, levels, st, d_splits, &ro.launches);
+    if (R.flags & SS_FLAG_GRAPH)
+        rc = batched_graph(dev, (char *)d_base, dtype, R, BC, B, items_cap, levels, st, d_splits, &ro.launches);
+    else
+        rc = batched_core((char *)d_base, dtype, R, BC, B, levels, st, d_splits, &ro.launches);
     if (rc)
         return rc;
     if (timing) {
@@ -539,9 +692,270 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
     return SS_OK;
 }
 
+// ------------------------------------------------------------ size classes
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, BatchClasses> g_tuned;  // (device, dtype)
+
+static_assert(sizeof(ss_batched_tuning) == 168, "ss_batched_tuning layout");
+
+int classes_from_table(const ss_batched_tuning *t, int w, BatchClasses *C)
+{
+    if (!t || t->nclass < 1 || t->nclass > (uint32_t)kMaxClasses || kMaxClasses != SS_MAX_CLASSES)
+        return fail_msg(SS_EINVAL, "tuning table: nclass out of range");
+    std::memset(C, 0, sizeof(*C));
+    C->n = t->nclass;
+    for (uint32_t c = 0; c < t->nclass; c++) {
+        const uint64_t b = t->b[c], line = b * (uint64_t)w, grp = t->group_bytes[c];
+        if (!b || (b & (b - 1)) || line < 64 || line > 4096)
+            return fail_msg(SS_EINVAL, "tuning table: b * element size must be a power of two in [64, 4096]");
+        if (grp < line || grp > 131072u || grp % line)
+            return fail_msg(SS_EINVAL, "tuning table: group_bytes must be a multiple of the line, at most 128 KiB");
+        if (c && t->max_len[c] < t->max_len[c - 1])
+            return fail_msg(SS_EINVAL, "tuning table: max_len must be non-decreasing");
+        C->log2b[c] = (uint32_t)ilog2(b);
+        C->s_max[c] = (uint32_t)(grp / line);
+        C->max_len[c] = c + 1 == t->nclass ? ~0ull : t->max_len[c];
+    }
+    return SS_OK;
+}
+
+void table_from_classes(const BatchClasses &C, int w, ss_batched_tuning *t)
+{
+    std::memset(t, 0, sizeof(*t));
+    t->nclass = C.n;
+    for (uint32_t c = 0; c < C.n; c++) {
+        t->b[c] = 1u << C.log2b[c];
+        t->group_bytes[c] = (uint32_t)(((uint64_t)C.s_max[c] << C.log2b[c]) * (uint64_t)w);
+        t->max_len[c] = C.max_len[c];
+    }
+}
+
+// A synthetic batch for one length class: keys from a SplitMix64 stream,
+// lengths log-uniform in (lo, hi], pivots at uniform quantiles of the key
+// range.
+__global__ void __launch_bounds__(256) k_tune_fill(char *base, uint64_t n, int w, uint64_t seed)
+{
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t z = splitmix64_at(seed, i);
+        if (w == 4)
+            reinterpret_cast<uint32_t *>(base)[i] = (uint32_t)(z >> 32);
+        else if (w == 8)
+            reinterpret_cast<uint64_t *>(base)[i] = z;
+        else {
+            reinterpret_cast<uint64_t *>(base)[2 * i] = z;
+            reinterpret_cast<uint64_t *>(base)[2 * i + 1] = i;
+        }
+    }
+}
+
+}  // namespace
+
+void batched_installed_classes(int dev, int dtype, const Resolved &R, BatchClasses *C)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_pair(dev, dtype));
+    if (it == g_tuned.end())
+        return;
+    for (uint32_t c = 0; c < it->second.n; c++)
+        if (((uint64_t)it->second.s_max[c] << it->second.log2b[c]) * R.w > R.tile)
+            return;  // the call's kernel tile is smaller than a tuned group
+    *C = it->second;
+}
+
+static int autotune(int dtype, hipStream_t st, ss_batched_tuning *out)
+{
+    const int w = elem_size(dtype);
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    Resolved R;
+    int rc = resolve_params(nullptr, dtype, &R);
+    if (rc)
+        return rc;
+    constexpr uint32_t NC = 7;
+    const uint64_t bound[NC] = {1ull << 10, 1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18, 1ull << 20, 1ull << 22};
+    const uint64_t lower[NC] = {1ull << 8, 1ull << 10, 1ull << 12, 1ull << 14, 1ull << 16, 1ull << 18, 1ull << 20};
+    const uint64_t total_target = 1ull << 24;
+    const uint32_t lines[4] = {128, 256, 512, 1024};
+    const uint32_t groups[3] = {32768, 65536, 131072};
+    // scratch: the batch, a pristine copy, pivots, splits
+    const size_t data_bytes = (size_t)(total_target + bound[NC - 1]) * w;
+    const size_t max_arrays = total_target / lower[0] + 2;
+    char *scratch = nullptr;
+    if ((e = hipMalloc((void **)&scratch, 2 * data_bytes + 2 * max_arrays * sizeof(uint64_t))) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail_msg(SS_ENOMEM, std::string("autotune scratch: ") + hipGetErrorString(e));
+    }
+    char *data = scratch, *pristine = scratch + data_bytes;
+    uint64_t *d_piv = reinterpret_cast<uint64_t *>(scratch + 2 * data_bytes);
+    uint64_t *d_split = d_piv + max_arrays;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(scratch);
+        return fail_msg(SS_EDEVICE, "hipEventCreate");
+    }
+    ss_batched_tuning T;
+    std::memset(&T, 0, sizeof(T));
+    T.nclass = NC;
+    std::vector<uint64_t> starts, lens, piv;
+    for (uint32_t c = 0; c < NC && rc == SS_OK; c++) {
+        // lengths: log-uniform in (lower, bound], from a counter-based stream
+        starts.clear();
+        lens.clear();
+        piv.clear();
+        uint64_t total = 0, cnt = 0;
+        const double l0 = std::log2((double)lower[c]), l1 = std::log2((double)bound[c]);
+        while (total < total_target || cnt == 0) {
+            const uint64_t z = splitmix64_at(0x7A11 + c, cnt);
+            const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+            uint64_t l = (uint64_t)std::exp2(l0 + (l1 - l0) * u);
+            l = l <= lower[c] ? lower[c] + 1 : l > bound[c] ? bound[c] : l;
+            const double q = 0.05 + 0.9 * (double)(splitmix64_at(0x9A11 + c, cnt) >> 11) * (1.0 / 9007199254740992.0);
+            starts.push_back(total);
+            lens.push_back(l);
+            piv.push_back(w == 4 ? (uint64_t)(q * 4294967296.0) : (uint64_t)(q * 18446744073709551615.0));
+            total += l;
+            cnt++;
+        }
+        const uint32_t num = (uint32_t)cnt;
+        if ((e = hipMemcpyAsync(d_piv, piv.data(), num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess) {
+            rc = fail_device(e, "hipMemcpyAsync");
+            break;
+        }
+        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, st, pristine, total, w, 0x5EED0000ull + c);
+        const uint64_t items_cap = batched_items_cap(lens.data(), num, 32768 / w);
+        float best = 1e30f;
+        uint32_t best_line = 512, best_group = 131072;
+        for (uint32_t li = 0; li < 4 && rc == SS_OK; li++) {
+            for (uint32_t gi = 0; gi < 3 && rc == SS_OK; gi++) {
+                const uint32_t line = lines[li], grp = groups[gi];
+                if (line < (uint32_t)w || line < 64)
+                    continue;
+                BatchClasses BC;
+                std::memset(&BC, 0, sizeof(BC));
+                BC.n = 1;
+                BC.max_len[0] = ~0ull;
+                BC.log2b[0] = (uint32_t)ilog2(line / w);
+                BC.s_max[0] = grp / line;
+                const uint32_t levels = batched_levels(bound[c], grp / w);
+                float t_best = 1e30f;
+                for (int rep = 0; rep < 3 && rc == SS_OK; rep++) {
+                    BatchState B;
+                    uint64_t *stage = nullptr;
+                    if ((rc = batched_state(dev, st, num, items_cap, &B, &stage)))
+                        break;
+                    B.pivot = d_piv;
+                    if ((e = hipStreamSynchronize(st)) != hipSuccess) {
+                        rc = fail_device(e, "hipStreamSynchronize");
+                        break;
+                    }
+                    std::memcpy(stage, starts.data(), num * sizeof(uint64_t));
+                    std::memcpy(stage + num, lens.data(), num * sizeof(uint64_t));
+                    if ((e = hipMemcpyAsync(B.start, stage, 2 * (size_t)num * sizeof(uint64_t),
+                                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+                        (e = hipMemcpyAsync(data, pristine, (size_t)total * w, hipMemcpyDeviceToDevice, st)) !=
+                            hipSuccess) {
+                        rc = fail_device(e, "hipMemcpyAsync");
+                        break;
+                    }
+                    uint32_t launches = 0;
+                    (void)hipEventRecord(e0, st);
+                    if ((rc = batched_core(data, dtype, R, BC, B, levels, st, d_split, &launches)))
+                        break;
+                    (void)hipEventRecord(e1, st);
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                        rc = fail_device(e, "hipEventSynchronize");
+                        break;
+                    }
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t_best = ms < t_best ? ms : t_best;
+                }
+                if (t_best < best) {
+                    best = t_best;
+                    best_line = line;
+                    best_group = grp;
+                }
+            }
+        }
+        T.b[c] = best_line / w;
+        T.group_bytes[c] = best_group;
+        T.max_len[c] = c + 1 == NC ? ~0ull : bound[c];
+        T.ms[c] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(scratch);
+    if (rc)
+        return rc;
+    BatchClasses C;
+    if ((rc = classes_from_table(&T, w, &C)))
+        return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_pair(dev, dtype)] = C;
+    }
+    if (out)
+        *out = T;
+    return SS_OK;
+}
+
 }  // namespace ss
 
 using namespace ss;
+
+extern "C" int ss_autotune_batched(int dtype, void *stream, ss_batched_tuning *out)
+{
+    if (!elem_size(dtype))
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    return autotune(dtype, (hipStream_t)stream, out);
+}
+
+extern "C" int ss_set_batched_tuning(int dtype, const ss_batched_tuning *t)
+{
+    const int w = elem_size(dtype);
+    if (!w)
+        return fail_msg(SS_EINVAL, "unknown dtype");
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tuned.erase(std::make_pair(dev, dtype));
+        return SS_OK;
+    }
+    BatchClasses C;
+    const int rc = classes_from_table(t, w, &C);
+    if (rc)
+        return rc;
+    g_tuned[std::make_pair(dev, dtype)] = C;
+    return SS_OK;
+}
+
+extern "C" int ss_get_batched_tuning(int dtype, ss_batched_tuning *t)
+{
+    const int w = elem_size(dtype);
+    if (!w || !t)
+        return fail_msg(SS_EINVAL, "unknown dtype or null table");
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    Resolved R;
+    int rc = resolve_params(nullptr, dtype, &R);
+    if (rc)
+        return rc;
+    BatchClasses C = batched_default_classes(R);
+    batched_installed_classes(dev, dtype, R, &C);
+    table_from_classes(C, w, t);
+    return SS_OK;
+}
 
 extern "C" int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, int dtype,
                                     const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,

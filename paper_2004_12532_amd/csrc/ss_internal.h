@@ -83,6 +83,7 @@ hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t 
 int fail_device(hipError_t e, const char *what);
 int fail_msg(int code, const std::string &msg);
 int elem_size(int dtype);
+int ilog2(uint64_t x);
 int check_array(const void *d_ptr, size_t n, int dtype);
 int resolve_params(const ss_params *p, int dtype, Resolved *r);
 int check_lines(uint64_t n, const Resolved &R);
@@ -92,6 +93,17 @@ int get_workspace(int dev, void *stream, Workspace **out);
 void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                   uint64_t *d_split, bool sync, RunOut *ro);
+
+// Size classes of a batched call: arrays of length <= max_len[c] (and above
+// the previous class's bound) use lines of 2^log2b[c] elements and groups of
+// at most s_max[c] lines.  One class covers every length by default.
+constexpr int kMaxClasses = 8;
+struct BatchClasses {
+    uint32_t n;
+    uint64_t max_len[kMaxClasses];
+    uint32_t log2b[kMaxClasses];
+    uint32_t s_max[kMaxClasses];
+};
 
 // Device state of a batched partition: one entry per array (see ss_batched.hip).
 struct BatchState {
@@ -105,14 +117,22 @@ struct BatchState {
     uint32_t *imap;    // item -> array
     uint64_t *vout;    // item -> splitting position
     uint64_t *ctl;     // [0] items of the current level, [1] open arrays
+    uint8_t *cls;      // size class of array k
     const uint32_t *count;  // device word holding the number of arrays (nullable: then num)
     uint32_t num;      // number of arrays, or the capacity when count is set (sizes the grids)
 };
 int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage);
 uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems);
 uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems);
-int batched_core(char *base, int dtype, const Resolved &R, BatchState &B, uint32_t levels, hipStream_t st,
-                 uint64_t *d_splits, uint32_t *launches);
+int batched_graph(int dev, char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B,
+                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches);
+void batched_graphs_forget(const void *state);
+BatchClasses batched_default_classes(const Resolved &R);
+void batched_installed_classes(int dev, int dtype, const Resolved &R, BatchClasses *C);
+int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B, uint32_t levels,
+                 hipStream_t st, uint64_t *d_splits, uint32_t *launches);
+
+uint64_t quicksort_leaf_cap(int dtype);
 
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats);

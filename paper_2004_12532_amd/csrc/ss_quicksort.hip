@@ -27,15 +27,11 @@
 // level L completes it reads the number and the longest length of level
 // L + 1's segments from mapped memory, and issues level L + 2 with the
 // number of partition levels that the longest segment needs.
-// Leaves: least-significant-digit radix sort with 8-bit digits over the key
-// (KV16 records move with their key).  Within a pass, each wavefront ranks 64
-// elements at a time: eight ballots give each lane the mask of lanes holding
-// the same digit, the lowest lane of that mask advances the wavefront's
-// counter for the digit, and a scan over (digit, wavefront) turns the
-// counters into destinations.  The sort is stable and needs no atomics.
+// Leaves are sorted by qleaf_sort (ss_leafsort.h).
 #include "ss_common.h"
 #include "ss_device.h"
 #include "ss_internal.h"
+#include "ss_leafsort.h"
 
 #include <cstring>
 #include <map>
@@ -44,11 +40,6 @@
 
 namespace ss {
 
-template <typename T>
-__device__ __forceinline__ uint64_t qkey(const T &x)
-{
-    return key_of(x);
-}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_qpivot(const char *base, const uint64_t *start, const uint64_t *len,
@@ -71,108 +62,6 @@ __global__ void __launch_bounds__(256) k_qpivot(const char *base, const uint64_t
     piv_dev[k] = p;
     if (piv_host)
         piv_host[k] = p;
-}
-
-template <typename T>
-struct Digit {
-    __device__ static __forceinline__ uint32_t of(const T &x, uint32_t sh) { return (uint32_t)(qkey(x) >> sh) & 255u; }
-};
-
-// One workgroup (1024 threads) sorts A[0, n), n <= CAP, by key.
-template <typename T, int CAP, int KEYBITS>
-__device__ void qleaf_sort(T *A, uint32_t n)
-{
-    constexpr int NT = 1024, NW = NT / 64;
-    constexpr int E = CAP / NT;  // elements per thread
-    __shared__ T buf[CAP];
-    __shared__ uint32_t cnt[NW][256];
-    __shared__ uint32_t dig_base[256];
-
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const uint64_t lt = (1ull << lane) - 1;
-
-    // Striped arrangement: element r of thread (wid, lane) is at
-    // index wid * 64 * E + r * 64 + lane, so element order is (wave, round, lane).
-    T x[E];
-    bool valid[E];
-    for (int r = 0; r < E; r++) {
-        const uint32_t idx = wid * 64 * E + r * 64 + lane;
-        valid[r] = idx < n;
-        if (valid[r])
-            x[r] = A[idx];
-    }
-    for (uint32_t sh = 0; sh < KEYBITS; sh += 8) {
-        for (int d = lane; d < 256; d += 64)
-            cnt[wid][d] = 0;
-        uint32_t pos[E];
-        for (int r = 0; r < E; r++) {
-            const uint32_t d = valid[r] ? Digit<T>::of(x[r], sh) : 0u;
-            uint64_t m = __ballot(valid[r]);
-            for (int bit = 0; bit < 8; bit++) {
-                const uint64_t bb = __ballot((d >> bit) & 1);
-                m &= ((d >> bit) & 1) ? bb : ~bb;
-            }
-            // m: valid lanes of this round holding digit d
-            const uint32_t before = (uint32_t)__popcll(m & lt);
-            const uint32_t old = valid[r] ? cnt[wid][d] : 0u;
-            pos[r] = old + before;
-            if (valid[r] && before == 0)
-                cnt[wid][d] = old + (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        // destinations: digit-major, then wavefront, then position within the wavefront
-        if (tid < 256) {
-            uint32_t tot = 0;
-            for (int w = 0; w < NW; w++)
-                tot += cnt[w][tid];
-            dig_base[tid] = tot;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            uint32_t v[4], s = 0;
-            for (int k = 0; k < 4; k++) {
-                v[k] = dig_base[tid * 4 + k];
-                s += v[k];
-            }
-            uint32_t inc = s;
-            for (int dd = 1; dd < 64; dd <<= 1) {
-                const uint32_t y = __shfl_up(inc, dd, 64);
-                if (lane >= dd)
-                    inc += y;
-            }
-            uint32_t run = inc - s;
-            for (int k = 0; k < 4; k++) {
-                dig_base[tid * 4 + k] = run;
-                run += v[k];
-            }
-        }
-        __syncthreads();
-        if (tid < 256) {
-            uint32_t run = dig_base[tid];
-            for (int w = 0; w < NW; w++) {
-                const uint32_t c = cnt[w][tid];
-                cnt[w][tid] = run;
-                run += c;
-            }
-        }
-        __syncthreads();
-        for (int r = 0; r < E; r++)
-            if (valid[r])
-                buf[cnt[wid][Digit<T>::of(x[r], sh)] + pos[r]] = x[r];
-        __syncthreads();
-        for (int r = 0; r < E; r++) {
-            const uint32_t idx = wid * 64 * E + r * 64 + lane;
-            if (valid[r])
-                x[r] = buf[idx];
-        }
-        __syncthreads();
-    }
-    for (int r = 0; r < E; r++) {
-        const uint32_t idx = wid * 64 * E + r * 64 + lane;
-        if (valid[r])
-            A[idx] = x[r];
-    }
-    __syncthreads();  // LDS is reused by the next leaf
 }
 
 // Leaves are taken by workgroups in turn (leaf b, b + grid, ...); each leaf
@@ -364,7 +253,8 @@ __device__ __forceinline__ void q_emit(const SegList &nxt, const QsCtl &C, uint6
 {
     if (l > C.leaf_cap) {
         const uint32_t i = atomicAdd(nxt.count, 1u);
-        if (i >= C.cap_segs) {
+        if (i >= C.cap_segs) {  // cannot happen (disjoint long segments); keep the count within capacity
+            atomicSub(nxt.count, 1u);
             atomicOr(C.overflow, 1u);
             return;
         }
@@ -375,6 +265,7 @@ __device__ __forceinline__ void q_emit(const SegList &nxt, const QsCtl &C, uint6
     } else if (l >= 2) {
         const uint32_t i = atomicAdd(C.leaf_count, 1u);
         if (i >= C.cap_leaves) {
+            atomicSub(C.leaf_count, 1u);
             atomicOr(C.overflow, 1u);
             return;
         }
@@ -488,7 +379,7 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     // word layout of the workspace
     const size_t words = 2 * 3 * capS + capS /*piv*/ + 2 * capL /*leaves*/ + 3 * capS /*lo, hi, split*/ +
                          (capS + 1) /*first*/ + items /*vout*/ + (capS + 1) / 2 + 1 /*g*/ + (items + 1) / 2 /*imap*/ +
-                         8 /*ctl*/ + 8 /*counts, report, overflow*/;
+                         capS / 8 + 1 /*cls*/ + 8 /*ctl*/ + 8 /*counts, report, overflow*/;
     QsDev *W = nullptr;
     int rc = qs_dev_reserve(dev, st, words * sizeof(uint64_t), &W);
     if (rc)
@@ -521,10 +412,12 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     B.vout = take(items);
     B.g = reinterpret_cast<uint32_t *>(take((capS + 1) / 2 + 1));
     B.imap = reinterpret_cast<uint32_t *>(take((items + 1) / 2));
+    B.cls = reinterpret_cast<uint8_t *>(take(capS / 8 + 1));
     B.ctl = take(8);
     B.num = (uint32_t)capS;
 
     const uint32_t grid_s = (uint32_t)((capS + 255) / 256);
+    const BatchClasses BC = batched_default_classes(R);
     hipLaunchKernelGGL(k_qinit, dim3(1), dim3(64), 0, st, LA, C, (uint64_t)n);
     (*launches)++;
     if (n <= cap) {
@@ -551,7 +444,8 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
         B.start = cur.start;
         B.len = cur.len;
         B.count = cur.count;
-        const int rc2 = batched_core(base, dtype, R, B, batched_levels(max_len, tile_elems), st, nullptr, launches);
+        const int rc2 =
+            batched_core(base, dtype, R, BC, B, batched_levels(max_len, tile_elems), st, nullptr, launches);
         if (rc2)
             return rc2;
         hipLaunchKernelGGL(k_qchildren, dim3(grid_s), dim3(256), 0, st, cur, nxt, C, (const uint64_t *)B.split);

@@ -1,26 +1,25 @@
 """Continuous-batching serving loop for partition and sort jobs.
 
 Jobs arrive over time (partition: split records by key < pivot; sort: the
-quicksort of Section 5.2).  A job is admitted when the device arena has room
-for its records (admission by bytes: the arena is the memory budget), its
-records are generated on the device, and from then on its work joins every
-*tick*:
+quicksort of Section 5.2).  A job is admitted when the memory budget has room
+for it -- its input bytes in the device arena plus the auxiliary bytes its
+pending segments, leaves and groups can occupy in the engine's device state
+(``ss_server_job_aux_bytes``) -- and a job slot is free.  Its records are then
+generated on the device and it is submitted to the device-resident engine
+(``ss_server_*`` in libss.so), which keeps every job's state on the device.
+Each tick is one fixed launch sequence over the pending work of all admitted
+jobs: one batched Smoothed Striding partition over every pending segment (a
+whole partition job, or one quicksort segment of a sort job), then the
+workgroup-local sort of every short sort segment.  Jobs that arrive while
+ticks run are admitted before the next tick, so work from many jobs overlaps
+in the same launches.  The host issues tick T + 1 before it looks at tick T's
+results (per-job done flags in mapped memory), so the device never idles on
+the host.  Every segment's result depends only on its own contents (lines are
+counted from the segment's start and the random offsets from its recursion
+level), so a job's output bytes are the same alone and inside any mix.
 
-* one batched partition (``ss_partition_segments``) over the segments of all
-  jobs with pending work: a whole waiting partition job, and one quicksort
-  level of every active sort job (a median-of-3 pivot per segment, or the
-  ``key <= p`` pass of a segment whose pivot was its minimum);
-* one workgroup-local sort (``ss_sort_segments``) of every sort segment that
-  has become short enough.
-
-Jobs that arrive while a tick runs are admitted before the next one, so work
-from many jobs overlaps in the same launches.  Every segment's result depends
-only on its own contents (lines are counted from the segment's start and the
-random offsets from its recursion level), so a job's output bytes are the
-same alone and inside any mix.
-
-All device work goes through the C ABI in libss.so; this module only keeps
-job state and the arena map.
+This module only keeps arrival times, the arena map and the admission
+accounting; all device work goes through the C ABI.
 """
 from __future__ import annotations
 
@@ -30,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (SS_KV16, make_params, median3_pivots, partition_segments, sort_segment_cap, sort_segments)
+from . import SS_KV16, ServerEngine, server_job_aux_bytes, sort_segment_cap
 
 U64MASK = (1 << 64) - 1
 RECORD_BYTES = 16  # SS_KV16
@@ -82,12 +81,11 @@ class Job:
     # runtime state
     off: int = -1
     block: int = 0
+    slot: int = -1
+    aux: int = 0
     admitted: float = -1.0
     done: float = -1.0
     split: int = -1
-    started: bool = False
-    segs: list = field(default_factory=list)    # sort: (start, len, mode, pivot) mode 0: median-of-3, 1: <= p
-    leaves: list = field(default_factory=list)  # sort: (start, len) waiting for the leaf sort
 
     @property
     def latency(self) -> float:
@@ -112,16 +110,22 @@ def make_jobs(count: int, rate_per_s: float, seed: int, p_partition: float = 0.7
 class Server:
     """Runs jobs to completion with continuous batching on one GPU."""
 
-    def __init__(self, budget_bytes: int = 64 << 30, device=None, keep_outputs: bool = False, params=None):
+    def __init__(self, budget_bytes: int = 64 << 30, device=None, keep_outputs: bool = False,
+                 max_jobs: int = 4096, max_segments: int = 1 << 16):
         import torch
         self.torch = torch
         self.device = device or torch.device("cuda", torch.cuda.current_device())
-        self.capacity = budget_bytes // RECORD_BYTES
+        # the budget holds the records' arena and the engine's auxiliary state
+        per_seg = server_job_aux_bytes(SS_KV16, 0, 0) - 64
+        self.aux_budget = min(budget_bytes // 64, max_segments * per_seg)
+        self.capacity = (budget_bytes - self.aux_budget) // RECORD_BYTES
         self.arena_t = torch.empty((self.capacity, 2), dtype=torch.int64, device=self.device)
         self.arena = Arena(self.capacity)
+        self.engine = ServerEngine(self.arena_t, max_jobs, max_segments, stream=torch.cuda.current_stream())
+        self.free_slots = list(range(max_jobs - 1, -1, -1))
+        self.aux_used = 0
         self.keep_outputs = keep_outputs
         self.outputs = {}
-        self.params = params or {}
         self.cap = sort_segment_cap(SS_KV16)
         self.ticks = 0
         self.max_batch = 0
@@ -133,83 +137,32 @@ class Server:
         workloads.splitmix64_torch(job.seed, 0, job.n, self.device, out=view[:, 0])
         view[:, 1] = self.torch.arange(job.n, dtype=self.torch.int64, device=self.device) + (job.job_id << 32)
 
-    def _classify(self, job: Job, start: int, length: int):
-        if length > self.cap:
-            job.segs.append((start, length, 0, 0))
-        elif length >= 2:
-            job.leaves.append((start, length))
+    def _admit(self, job: Job, t0: float) -> bool:
+        kind = 0 if job.kind == "partition" else 1
+        aux = server_job_aux_bytes(SS_KV16, kind, job.n)
+        if not self.free_slots or self.aux_used + aux > self.aux_budget:
+            return False
+        got = self.arena.alloc(job.n)
+        if got is None:
+            return False
+        job.off, job.block = got
+        job.slot = self.free_slots.pop()
+        job.aux = aux
+        self.aux_used += aux
+        job.admitted = time.perf_counter() - t0
+        self._generate(job)
+        self.engine.submit(job.slot, job.off, job.n, kind, job.pivot)
+        return True
 
-    def _finish(self, job: Job, now: float):
+    def _finish(self, job: Job, now: float, split: int):
         job.done = now
+        if job.kind == "partition":
+            job.split = split
         if self.keep_outputs:
             self.outputs[job.job_id] = self.arena_t[job.off:job.off + job.n].cpu().numpy().view(np.uint64).copy()
         self.arena.release(job.off, job.block)
-
-    # ----------------------------------------------------------------- one tick
-    def _tick(self, active: list, t0: float):
-        torch = self.torch
-        # segments of this tick: (job, start, len, mode, host pivot or None)
-        work = []
-        for job in active:
-            if job.kind == "partition":
-                if not job.started:
-                    work.append((job, job.off, job.n, 2, job.pivot))
-                    job.started = True
-            else:
-                for (s, l, mode, p) in job.segs:
-                    work.append((job, s, l, mode, p if mode == 1 else None))
-                job.segs = []
-        if work:
-            m = len(work)
-            starts = np.array([w[1] for w in work], dtype=np.uint64)
-            lens = np.array([w[2] for w in work], dtype=np.uint64)
-            pivots = np.array([w[4] if w[4] is not None else 0 for w in work], dtype=np.uint64)
-            need = [i for i, w in enumerate(work) if w[4] is None]
-            d_piv = torch.empty(m, dtype=torch.int64, device=self.device)
-            if need:
-                d_tmp = torch.empty(len(need), dtype=torch.int64, device=self.device)
-                hp = median3_pivots(self.arena_t, starts[need], lens[need], d_tmp, host=True)
-                pivots[need] = hp
-            d_piv.copy_(torch.from_numpy(pivots.view(np.int64)))
-            d_split = torch.empty(m, dtype=torch.int64, device=self.device)
-            partition_segments(self.arena_t, starts, lens, d_piv, d_split, **self.params)
-            splits = d_split.cpu().numpy().view(np.uint64)
-            self.max_batch = max(self.max_batch, m)
-            now = time.perf_counter() - t0
-            for i, (job, s, l, mode, _) in enumerate(work):
-                sp = int(splits[i])
-                if mode == 2:  # partition job
-                    job.split = sp
-                    continue
-                p = int(pivots[i])
-                if mode == 0 and sp == 0:
-                    # the pivot is the segment's minimum: gather its copies with key <= p
-                    if p == U64MASK:
-                        continue  # every key equals the largest key: already sorted
-                    job.segs.append((s, l, 1, p + 1))
-                    continue
-                if mode == 0:
-                    self._classify(job, s, sp)
-                    self._classify(job, s + sp, l - sp)
-                else:
-                    self._classify(job, s + sp, l - sp)  # [s, s + sp) holds only the pivot's key
-        leaves = [(job, s, l) for job in active if job.kind == "sort" for (s, l) in job.leaves]
-        if leaves:
-            sort_segments(self.arena_t, np.array([x[1] for x in leaves], dtype=np.uint64),
-                          np.array([x[2] for x in leaves], dtype=np.uint64))
-            for job in active:
-                job.leaves = []
-        torch.cuda.synchronize()
-        self.ticks += 1
-        now = time.perf_counter() - t0
-        still = []
-        for job in active:
-            finished = job.split >= 0 if job.kind == "partition" else (not job.segs and not job.leaves)
-            if finished:
-                self._finish(job, now)
-            else:
-                still.append(job)
-        return still
+        self.free_slots.append(job.slot)
+        self.aux_used -= job.aux
 
     # ----------------------------------------------------------------- run
     def run(self, jobs: list, realtime: bool = True):
@@ -226,28 +179,34 @@ class Server:
             while qi < len(pending) and (not realtime or pending[qi].arrival <= now):
                 waiting.append(pending[qi])
                 qi += 1
-            # FIFO admission while the arena has room
-            while waiting:
-                job = waiting[0]
-                got = self.arena.alloc(job.n)
-                if got is None:
-                    if not active:
-                        raise RuntimeError("job %d (%d records) does not fit the memory budget" % (job.job_id, job.n))
-                    break
-                waiting.pop(0)
-                job.off, job.block = got
-                job.admitted = time.perf_counter() - t0
-                self._generate(job)
-                if job.kind == "sort":
-                    self._classify(job, job.off, job.n)
-                    if not job.segs and not job.leaves:
-                        job.split = 0
-                active.append(job)
+            # FIFO admission while the budget has room
+            while waiting and self._admit(waiting[0], t0):
+                active.append(waiting.pop(0))
+            if waiting and not active:
+                raise RuntimeError("job %d (%d records) does not fit the memory budget"
+                                   % (waiting[0].job_id, waiting[0].n))
             if not active:
                 if qi < len(pending):
                     time.sleep(max(0.0, min(0.001, pending[qi].arrival - now)))
                 continue
-            active = self._tick(active, t0)
+            self.engine.tick(max(j.n for j in active))
+            self.ticks += 1
+            self.max_batch = max(self.max_batch, len(active))
+            # look at the results of the previous tick while this one runs
+            self.engine.wait(1)
+            now = time.perf_counter() - t0
+            still = []
+            for job in active:
+                fin, split = self.engine.done(job.slot)
+                if fin:
+                    self._finish(job, now, split)
+                else:
+                    still.append(job)
+            active = still
+        self.engine.wait(0)
+        flags = self.engine.status()
+        if flags:
+            raise RuntimeError("serving engine capacity exceeded (flags %d)" % flags)
         return jobs
 
 

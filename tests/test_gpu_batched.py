@@ -135,3 +135,71 @@ def test_segments_reject_overlap(ss):
     sp = torch.zeros(2, dtype=torch.int64, device="cuda")
     with pytest.raises(ss.SSError):
         ss.partition_segments(t, [0, 50], [100, 100], pv, sp)
+
+
+@pytest.mark.parametrize("kind", ["u64", "kv"])
+def test_batched_graph_replays_match_eager(ss, kind):
+    """The level chain replayed from a captured HIP graph gives the eager call's
+    bytes on every replay, with eager work and synchronizations in between."""
+    import torch
+    lengths = np.concatenate([[0, 1, 5, 16385],
+                              workloads.lognormal_lengths(200, 4, median_log2=12.0, sigma_log2=1.5, lo=1,
+                                                          hi=1 << 18)]).astype(np.int64)
+    data, offsets, pivots = _batch(kind, lengths, 8)
+    eager_out, eager_splits, _ = _run_batched(ss, data, offsets, pivots)
+    _check(data, eager_out, offsets, pivots, eager_splits)
+    pristine = to_device(data)
+    t = pristine.clone()
+    pv = torch.from_numpy(pivots.view(np.int64).copy()).cuda()
+    sp = torch.empty((len(pivots),), dtype=torch.int64, device="cuda")
+    for rep in range(4):
+        t.copy_(pristine)
+        sp.fill_(-7)
+        noise = torch.randn(1 << 16, device="cuda").sum()      # unrelated eager work between replays
+        ss.partition_batched(t, offsets, pv, sp, graph=True)
+        torch.cuda.synchronize()
+        assert torch.isfinite(noise)
+        assert np.array_equal(sp.cpu().numpy().view(np.uint64), eager_splits), rep
+        assert np.array_equal(to_host(t, data), eager_out), rep
+
+
+def test_size_class_tables_keep_parity(ss):
+    """Per-class line and group sizes change the work, never the result."""
+    table = {"classes": [{"max_len": 1 << 10, "b": 16, "group_bytes": 32768},
+                         {"max_len": 1 << 14, "b": 32, "group_bytes": 65536},
+                         {"max_len": 1 << 62, "b": 128, "group_bytes": 131072}]}
+    try:
+        ss.set_batched_tuning("u64", table)
+        got = ss.get_batched_tuning("u64")["classes"]
+        assert [(c["b"], c["group_bytes"]) for c in got] == [(16, 32768), (32, 65536), (128, 131072)]
+        assert got[-1]["max_len"] == (1 << 64) - 1                 # the last class is unbounded
+        lengths = np.concatenate([[0, 1, 1000, 1024, 1025, 16384, 16385, 70000],
+                                  workloads.lognormal_lengths(200, 2, median_log2=13.0, sigma_log2=2.0, lo=1,
+                                                              hi=1 << 19)]).astype(np.int64)
+        data, offsets, pivots = _batch("u64", lengths, 6)
+        out, splits, st = _run_batched(ss, data, offsets, pivots)
+        _check(data, out, offsets, pivots, splits)
+        for bad in ({"classes": [{"max_len": 5, "b": 3, "group_bytes": 32768}]},
+                    {"classes": [{"max_len": 5, "b": 16, "group_bytes": 262144}]},
+                    {"classes": [{"max_len": 9, "b": 16, "group_bytes": 32768},
+                                 {"max_len": 5, "b": 16, "group_bytes": 32768}]}):
+            with pytest.raises(ss.SSError):
+                ss.set_batched_tuning("u64", bad)
+    finally:
+        ss.set_batched_tuning("u64", None)
+    assert ss.get_batched_tuning("u64")["classes"][0]["group_bytes"] == 131072
+
+
+@pytest.mark.parametrize("kind", ["u32", "kv"])
+def test_autotune_installs_a_table_that_keeps_parity(ss, kind):
+    try:
+        t = ss.autotune_batched(kind)
+        assert len(t["classes"]) == 7
+        assert all(c["ms"] > 0 for c in t["classes"])
+        assert ss.get_batched_tuning(kind)["classes"] == [{**c, "ms": 0.0} for c in t["classes"]]
+        lengths = workloads.lognormal_lengths(400, 12, median_log2=13.0, sigma_log2=2.0, lo=1, hi=1 << 20)
+        data, offsets, pivots = _batch(kind, lengths.astype(np.int64), 13)
+        out, splits, _ = _run_batched(ss, data, offsets, pivots)
+        _check(data, out, offsets, pivots, splits)
+    finally:
+        ss.set_batched_tuning(kind, None)
