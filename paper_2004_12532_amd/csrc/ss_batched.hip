@@ -3,9 +3,9 @@
 // Partition Step applied to every array at once).
 //
 // Device state, one entry per array k: its current region [lo_k, hi_k)
-// (absolute element indices into the base), its pivot, its number of groups
-// g_k at this level, and its split once found.  A level is four launches with
-// no host decision in between:
+// (absolute element indices into the base), its pivot, its size class, its
+// number of groups g_k at this level, and its split once found.  A level is
+// three launches with no host decision in between:
 //   k_binit / k_bstep  per array (one wavefront): fold the previous level's
 //             splitting positions of its groups into [v_min, v_max) -- a
 //             region left with one group or none is finished (split = v_min),
@@ -13,9 +13,10 @@
 //             geometry g_k from that region;
 //   k_bscan   one workgroup: exclusive scan of g_k -> the array's first item,
 //             staged through LDS so that every global access is coalesced;
-//   k_bfill   item map: item t -> array k (one wavefront per array);
 //   k_blevel  persistent: every workgroup takes items t = bid, bid + grid, ...,
-//             partitions group t - first_k of array k exactly as the
+//             finds the array k of item t (binary search over the first-item
+//             offsets in LDS; for very large batches an item map written by
+//             k_bfill), partitions group t - first_k of array k exactly as the
 //             single-array kernel does and writes the group's splitting
 //             position v.
 // The number of levels is planned on the host from the longest array (each
@@ -45,10 +46,18 @@
 
 namespace ss {
 
+// With search set, the level kernel finds an item's array by binary search
+// over the first-item offsets, copied into dynamic LDS at its start, instead
+// of reading an item map: for up to 16399 arrays with the 128 KiB-group
+// kernel (one workgroup per CU either way; 128 KiB of LDS), up to 4095 with
+// the smaller ones (whose occupancy the LDS must not cut).
+constexpr uint32_t kSearchMaxBig = 16400, kSearchMaxSmall = 4096;
+
 struct BatchGeom {
     char *base;
     uint64_t seed;
     uint32_t level;
+    uint32_t search;
     BatchClasses C;
 };
 
@@ -81,8 +90,90 @@ __global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
     }
 }
 
+// Exclusive scan of g over all arrays (first item of every array), the item
+// count ctl[0] and the count of open arrays ctl[1].  One workgroup; chunks of
+// kScanChunk entries are staged through LDS so that global reads and writes
+// are coalesced, and each thread scans kScanPer consecutive entries.
+constexpr int kScanNT = 1024, kScanPer = 8, kScanChunk = kScanNT * kScanPer;
+
+struct ScanSmem {
+    uint64_t tile[kScanChunk];
+    uint64_t wsum[kScanNT / 64], wopen[kScanNT / 64];
+};
+
+// Exclusive scan of g over all arrays by one workgroup of kScanNT threads.
+__device__ void scan_groups(const BatchState &B, ScanSmem &S)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint64_t carry = 0, ocarry = 0;
+    const uint32_t num = bnum(B);
+    for (uint32_t c0 = 0; c0 < num; c0 += kScanChunk) {
+        const uint32_t m = num - c0 < (uint32_t)kScanChunk ? num - c0 : (uint32_t)kScanChunk;
+        for (uint32_t j = tid; j < m; j += kScanNT)
+            S.tile[j] = B.g[c0 + j];
+        __syncthreads();
+        uint64_t v[kScanPer], s = 0, open = 0;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const uint32_t j = tid * kScanPer + r;
+            v[r] = j < m ? S.tile[j] : 0;
+            s += v[r];
+            open += v[r] != 0;
+        }
+        uint64_t inc = s, oinc = open;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(inc, d, 64), z = __shfl_up(oinc, d, 64);
+            if (lane >= d) {
+                inc += y;
+                oinc += z;
+            }
+        }
+        if (lane == 63) {
+            S.wsum[wid] = inc;
+            S.wopen[wid] = oinc;
+        }
+        __syncthreads();
+        uint64_t off = carry, tot = 0, otot = 0;
+        for (int w = 0; w < kScanNT / 64; w++) {
+            if (w < wid)
+                off += S.wsum[w];
+            tot += S.wsum[w];
+            otot += S.wopen[w];
+        }
+        uint64_t run = off + inc - s;
+#pragma unroll
+        for (int r = 0; r < kScanPer; r++) {
+            const uint32_t j = tid * kScanPer + r;
+            if (j < m)
+                S.tile[j] = run;
+            run += v[r];
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < m; j += kScanNT)
+            B.first[c0 + j] = S.tile[j];
+        carry += tot;
+        ocarry += otot;
+        __syncthreads();  // tile and wsum are rewritten by the next chunk
+    }
+    if (tid == 0) {
+        B.first[num] = carry;
+        B.ctl[0] = carry;
+        B.ctl[1] = ocarry;
+    }
+}
+
+__global__ void __launch_bounds__(kScanNT) k_bscan(BatchState B)
+{
+    __shared__ ScanSmem S;
+    scan_groups(B, S);
+}
+
 // Later levels: fold the previous level's splitting positions of array k
-// (one wavefront per array), then plan the next level.
+// (one wavefront per array), then plan the next level.  (A separate
+// single-workgroup scan follows: handing the scan to the last workgroup to
+// finish here would need device-scope fences and a shared ticket, which cost
+// more than the launch they save on a GPU whose XCDs have separate L2s.)
 __global__ void __launch_bounds__(256) k_bstep(BatchState B, BatchGeom Gm)
 {
     const uint32_t num = bnum(B);
@@ -112,75 +203,6 @@ __global__ void __launch_bounds__(256) k_bstep(BatchState B, BatchGeom Gm)
     }
 }
 
-// Exclusive scan of g over all arrays (first item of every array), the item
-// count ctl[0] and the count of open arrays ctl[1].  One workgroup; chunks of
-// kScanChunk entries are staged through LDS so that global reads and writes
-// are coalesced, and each thread scans kScanPer consecutive entries.
-constexpr int kScanNT = 1024, kScanPer = 8, kScanChunk = kScanNT * kScanPer;
-
-__global__ void __launch_bounds__(kScanNT) k_bscan(BatchState B)
-{
-    __shared__ uint64_t tile[kScanChunk];
-    __shared__ uint64_t wsum[kScanNT / 64], wopen[kScanNT / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint64_t carry = 0, ocarry = 0;
-    const uint32_t num = bnum(B);
-    for (uint32_t c0 = 0; c0 < num; c0 += kScanChunk) {
-        const uint32_t m = num - c0 < (uint32_t)kScanChunk ? num - c0 : (uint32_t)kScanChunk;
-        for (uint32_t j = tid; j < m; j += kScanNT)
-            tile[j] = B.g[c0 + j];
-        __syncthreads();
-        uint64_t v[kScanPer], s = 0, open = 0;
-#pragma unroll
-        for (int r = 0; r < kScanPer; r++) {
-            const uint32_t j = tid * kScanPer + r;
-            v[r] = j < m ? tile[j] : 0;
-            s += v[r];
-            open += v[r] != 0;
-        }
-        uint64_t inc = s, oinc = open;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t y = __shfl_up(inc, d, 64), z = __shfl_up(oinc, d, 64);
-            if (lane >= d) {
-                inc += y;
-                oinc += z;
-            }
-        }
-        if (lane == 63) {
-            wsum[wid] = inc;
-            wopen[wid] = oinc;
-        }
-        __syncthreads();
-        uint64_t off = carry, tot = 0, otot = 0;
-        for (int w = 0; w < kScanNT / 64; w++) {
-            if (w < wid)
-                off += wsum[w];
-            tot += wsum[w];
-            otot += wopen[w];
-        }
-        uint64_t run = off + inc - s;
-#pragma unroll
-        for (int r = 0; r < kScanPer; r++) {
-            const uint32_t j = tid * kScanPer + r;
-            if (j < m)
-                tile[j] = run;
-            run += v[r];
-        }
-        __syncthreads();
-        for (uint32_t j = tid; j < m; j += kScanNT)
-            B.first[c0 + j] = tile[j];
-        carry += tot;
-        ocarry += otot;
-        __syncthreads();  // tile and wsum are rewritten by the next chunk
-    }
-    if (tid == 0) {
-        B.first[num] = carry;
-        B.ctl[0] = carry;
-        B.ctl[1] = ocarry;
-    }
-}
-
 __global__ void __launch_bounds__(256) k_bfill(BatchState B)
 {
     const uint32_t num = bnum(B);
@@ -200,11 +222,33 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
     constexpr int MAXS = Ctx::NVEC * 16 / 64;
     __shared__ uint32_t xoff[MAXS];
     __shared__ uint32_t cnt[Ctx::E + 1];
+    extern __shared__ uint64_t sfirst[];  // num + 1 entries when Gm.search
 
     const int tid = threadIdx.x;
     const uint64_t total = B.ctl[0];
+    uint32_t num = 0;
+    if (Gm.search) {
+        num = bnum(B);
+        for (uint32_t j = tid; j <= num; j += NT)
+            sfirst[j] = B.first[j];
+        __syncthreads();
+    }
     for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t k = B.imap[t];
+        uint32_t k;
+        if (Gm.search) {
+            // the last array whose first item is <= t (arrays with no items share their successor's offset)
+            uint32_t lo = 0, hi = num;  // sfirst[lo] <= t < sfirst[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (sfirst[mid] <= t)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            k = lo;
+        } else {
+            k = B.imap[t];
+        }
         const uint32_t i = (uint32_t)(t - B.first[k]);
         const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
         const uint32_t cl = B.cls[k], log2b = Gm.C.log2b[cl];
@@ -295,7 +339,14 @@ std::map<std::pair<int, void *>, BatchWork> g_b;
 template <typename T, int NT, int NV>
 hipError_t launch_blevel(uint32_t grid, const BatchState &B, const BatchGeom &G, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_blevel<T, NT, NV>), dim3(grid), dim3(NT), 0, st, B, G);
+    const size_t shmem = G.search ? ((size_t)B.num + 1) * sizeof(uint64_t) : 0;
+    if (shmem > 32768) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blevel<T, NT, NV>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL((k_blevel<T, NT, NV>), dim3(grid), dim3(NT), shmem, st, B, G);
     return hipGetLastError();
 }
 
@@ -394,6 +445,7 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
                    nb4 = std::min<uint32_t>((B.num + 3) / 4, 2048u);
     if (levels < 1)
         levels = 1;
+    Gm.search = B.num < (tile == 131072u ? kSearchMaxBig : kSearchMaxSmall) ? 1u : 0u;
     for (uint32_t level = 0; level < levels; level++) {
         Gm.level = level;
         if (level == 0)
@@ -401,10 +453,14 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
         else
             hipLaunchKernelGGL(k_bstep, dim3(nb4), dim3(256), 0, st, B, Gm);
         hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kScanNT), 0, st, B);
-        hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
+        *launches += 2;
+        if (!Gm.search) {
+            hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
+            (*launches)++;
+        }
         if ((e = V->launch(P, B, Gm, st)) != hipSuccess)
             return fail_device(e, "batched level launch");
-        *launches += 4;
+        (*launches)++;
     }
     Gm.level = levels;
     hipLaunchKernelGGL(k_bstep, dim3(nb4), dim3(256), 0, st, B, Gm);
@@ -414,7 +470,7 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
     case SS_U64: hipLaunchKernelGGL(k_bcleanup<uint64_t>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
     default: hipLaunchKernelGGL(k_bcleanup<KV>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
     }
-    *launches += 2;
+    (*launches)++;
     if (d_splits) {
         hipLaunchKernelGGL(k_bfinish, dim3(nb256), dim3(256), 0, st, B, d_splits);
         (*launches)++;
