@@ -115,7 +115,13 @@ typedef struct ss_params {
  *                  straight to its destination (no LDS tile, higher occupancy).
  * SS_ENGINE_REGS2: as SS_ENGINE_REGS with two register buffers: the next
  *                  group's loads are in flight while the current one is
- *                  partitioned (32768- or 65536-byte groups). */
+ *                  partitioned (32768- or 65536-byte groups).
+ * SS_ENGINE_AUTO : SS_ENGINE_REGS with 131072-byte groups, except for SS_U32
+ *                  in ss_partition / ss_partition_ex, which use SS_ENGINE_LDS
+ *                  with 32768-byte groups (four 4-byte scattered stores per
+ *                  16-byte vector cost more than staging through LDS).  The
+ *                  batched calls, the quicksort and the serving engine always
+ *                  use the register engine. */
 #define SS_ENGINE_AUTO 0u
 #define SS_ENGINE_LDS 1u
 #define SS_ENGINE_REGS 2u

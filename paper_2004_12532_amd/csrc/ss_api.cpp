@@ -150,7 +150,7 @@ int ilog2(uint64_t x)
 }
 
 // Resolve defaults and validate parameters (no device work).
-int resolve_params(const ss_params *p, int dtype, Resolved *r)
+int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_engine)
 {
     const int w = elem_size(dtype);
     if (!w)
@@ -165,7 +165,10 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r)
         return fail_msg(SS_EINVAL, "unknown flags");
     if (q.engine > SS_ENGINE_REGS2)
         return fail_msg(SS_EINVAL, "unknown engine");
-    const uint32_t engine = q.engine ? q.engine : kDefaultEngine;
+    uint32_t engine = q.engine ? q.engine : auto_engine;
+    if (!q.engine && engine == SS_ENGINE_LDS &&
+        (q.tile_bytes == 131072u || (q.flags & (SS_FLAG_STREAM | SS_FLAG_XCD_ORDER))))
+        engine = SS_ENGINE_REGS;  // options only the register engine has
     const uint32_t tile = q.tile_bytes ? q.tile_bytes
                          : engine == SS_ENGINE_LDS  ? 32768u
                          : engine == SS_ENGINE_REGS2 ? 65536u
@@ -440,7 +443,8 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
     if (rc)
         return rc;
     Resolved R;
-    rc = resolve_params(p, dtype, &R);
+    // single-array calls: u32 groups go through an LDS tile (see SS_ENGINE_AUTO)
+    rc = resolve_params(p, dtype, &R, dtype == SS_U32 ? (uint32_t)SS_ENGINE_LDS : kDefaultEngine);
     if (rc)
         return rc;
     if (R.algo == SS_LOWSPACE)

@@ -85,7 +85,7 @@ int fail_msg(int code, const std::string &msg);
 int elem_size(int dtype);
 int ilog2(uint64_t x);
 int check_array(const void *d_ptr, size_t n, int dtype);
-int resolve_params(const ss_params *p, int dtype, Resolved *r);
+int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_engine = kDefaultEngine);
 int check_lines(uint64_t n, const Resolved &R);
 int device_info(int dev, int *cus, int *lds);
 int occupancy(int dev, const void *fn, int nt, int *blocks);
