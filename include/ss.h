@@ -120,8 +120,9 @@ typedef struct ss_params {
  *                  in ss_partition / ss_partition_ex, which use SS_ENGINE_LDS
  *                  with 32768-byte groups (four 4-byte scattered stores per
  *                  16-byte vector cost more than staging through LDS).  The
- *                  batched calls, the quicksort and the serving engine always
- *                  use the register engine. */
+ *                  batched calls, the quicksort and the serving engine use
+ *                  the register engine unless p->engine asks for the LDS one
+ *                  (32768- or 65536-byte groups). */
 #define SS_ENGINE_AUTO 0u
 #define SS_ENGINE_LDS 1u
 #define SS_ENGINE_REGS 2u

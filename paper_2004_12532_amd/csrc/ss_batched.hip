@@ -34,6 +34,7 @@
 #include "ss_common.h"
 #include "ss_device.h"
 #include "ss_internal.h"
+#include "ss_ldsctx.h"
 #include "ss_levelctx.h"
 
 #include <algorithm>
@@ -297,6 +298,87 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
     }
 }
 
+// The same level with the LDS-tile group body (ss_ldsctx.h).
+template <typename T, int NT, int TILE>
+__global__ void __launch_bounds__(NT) k_blevel_lds(BatchState B, BatchGeom Gm)
+{
+    using Ctx = LdsCtx<T, NT, TILE>;
+    constexpr int W = Ctx::W;
+    constexpr int MAXS = TILE / 64;
+    __shared__ v4u tile[Ctx::NVEC];
+    __shared__ uint32_t xoff[MAXS];
+    __shared__ uint32_t wtot[Ctx::E], wpre[Ctx::E + 1];
+    extern __shared__ uint64_t sfirst[];  // num + 1 entries when Gm.search
+
+    const int tid = threadIdx.x;
+    const uint64_t total = B.ctl[0];
+    uint32_t num = 0;
+    if (Gm.search) {
+        num = bnum(B);
+        for (uint32_t j = tid; j <= num; j += NT)
+            sfirst[j] = B.first[j];
+        __syncthreads();
+    }
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        uint32_t k;
+        if (Gm.search) {
+            uint32_t lo = 0, hi = num;  // sfirst[lo] <= t < sfirst[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (sfirst[mid] <= t)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            k = lo;
+        } else {
+            k = B.imap[t];
+        }
+        const uint32_t i = (uint32_t)(t - B.first[k]);
+        const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
+        const uint32_t cl = B.cls[k], log2b = Gm.C.log2b[cl];
+        const Geo G = plan_geo(lo - start, hi - start, log2b, Gm.C.s_max[cl]);
+        Ctx x;
+        x.g = G.g;
+        x.s = G.s;
+        x.fp = G.fp;
+        x.real_end = (uint64_t)G.fp + (hi - lo);
+        x.A0 = Gm.base + (lo - G.fp) * W;
+        x.log2b = log2b;
+        x.vpl_log2 = log2b + Ctx::LOG2W - 4;
+        x.nvec = G.s << x.vpl_log2;
+        x.pivot = B.pivot[k];
+        x.xoff = xoff;
+        x.tile = tile;
+        x.wtot = wtot;
+        x.wpre = wpre;
+        x.tid = tid;
+        x.lane = tid & 63;
+        x.wid = tid >> 6;
+        for (uint32_t j = tid; j < G.s; j += NT)
+            xoff[j] = G.g > 1 ? chunk_offset(Gm.seed, Gm.level, j, G.g) : 0u;
+        __syncthreads();
+        v4u buf[Ctx::NV];
+        uint32_t partial;
+        x.load(buf, i, partial);
+        const uint32_t c = x.partition_store(buf, i, partial);
+        if (tid == 0) {
+            uint64_t vi;
+            if (c >= (G.s << log2b)) {
+                vi = hi;
+            } else {
+                const uint32_t j = c >> log2b;
+                uint32_t r = xoff[j] + i;
+                r = r >= G.g ? r - G.g : r;
+                const uint64_t vp = (((uint64_t)j * G.g + r) << log2b) + (c & ((1u << log2b) - 1));
+                vi = vp >= x.real_end ? hi : lo + (vp - G.fp);
+            }
+            B.vout[t] = vi;
+        }
+        __syncthreads();  // LDS reused by the next item
+    }
+}
+
 // Arrays still open after the last level: one workgroup each partitions the
 // remaining region serially (block two-pointer exchange).
 template <typename T>
@@ -356,25 +438,54 @@ const void *blevel_fn()
     return reinterpret_cast<const void *>(&k_blevel<T, NT, NV>);
 }
 
+template <typename T, int NT, int TILE>
+hipError_t launch_blevel_lds(uint32_t grid, const BatchState &B, const BatchGeom &G, hipStream_t st)
+{
+    const size_t shmem = G.search ? ((size_t)B.num + 1) * sizeof(uint64_t) : 0;
+    if (shmem > 32768) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_blevel_lds<T, NT, TILE>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL((k_blevel_lds<T, NT, TILE>), dim3(grid), dim3(NT), shmem, st, B, G);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int TILE>
+const void *blevel_lds_fn()
+{
+    return reinterpret_cast<const void *>(&k_blevel_lds<T, NT, TILE>);
+}
+
 struct BVariant {
     int dtype;
+    uint32_t engine;
     uint32_t tile;
     int nt;
     hipError_t (*launch)(uint32_t, const BatchState &, const BatchGeom &, hipStream_t);
     const void *(*fn)();
 };
 
-#define SS_BV(D, T, NT, NV) {D, NT * NV * 16, NT, &launch_blevel<T, NT, NV>, &blevel_fn<T, NT, NV>}
+#define SS_BV(D, T, NT, NV) \
+    {D, SS_ENGINE_REGS, NT * NV * 16, NT, &launch_blevel<T, NT, NV>, &blevel_fn<T, NT, NV>}
+#define SS_BVL(D, T, NT, TILE) \
+    {D, SS_ENGINE_LDS, TILE, NT, &launch_blevel_lds<T, NT, TILE>, &blevel_lds_fn<T, NT, TILE>}
 
-const BVariant *pick_bvariant(int dtype, uint32_t tile)
+const BVariant *pick_bvariant(int dtype, uint32_t engine, uint32_t tile)
 {
     static const BVariant v[] = {
-        SS_BV(SS_U32, uint32_t, 256, 8),  SS_BV(SS_U64, uint64_t, 256, 8),  SS_BV(SS_KV16, KV, 256, 8),
-        SS_BV(SS_U32, uint32_t, 512, 8),  SS_BV(SS_U64, uint64_t, 512, 8),  SS_BV(SS_KV16, KV, 512, 8),
-        SS_BV(SS_U32, uint32_t, 512, 16), SS_BV(SS_U64, uint64_t, 512, 16), SS_BV(SS_KV16, KV, 512, 16),
+        SS_BV(SS_U32, uint32_t, 256, 8),         SS_BV(SS_U64, uint64_t, 256, 8),
+        SS_BV(SS_KV16, KV, 256, 8),              SS_BV(SS_U32, uint32_t, 512, 8),
+        SS_BV(SS_U64, uint64_t, 512, 8),         SS_BV(SS_KV16, KV, 512, 8),
+        SS_BV(SS_U32, uint32_t, 512, 16),        SS_BV(SS_U64, uint64_t, 512, 16),
+        SS_BV(SS_KV16, KV, 512, 16),             SS_BVL(SS_U32, uint32_t, 256, 32768),
+        SS_BVL(SS_U64, uint64_t, 256, 32768),    SS_BVL(SS_KV16, KV, 256, 32768),
+        SS_BVL(SS_U32, uint32_t, 256, 65536),    SS_BVL(SS_U64, uint64_t, 256, 65536),
+        SS_BVL(SS_KV16, KV, 256, 65536),
     };
     for (const BVariant &x : v)
-        if (x.dtype == dtype && x.tile == tile)
+        if (x.dtype == dtype && x.engine == engine && x.tile == tile)
             return &x;
     return nullptr;
 }
@@ -424,8 +535,9 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
     int rc = device_info(dev, &cus, &lds);
     if (rc)
         return rc;
-    const uint32_t tile = R.engine == SS_ENGINE_REGS && R.tile ? R.tile : 131072u;
-    const BVariant *V = pick_bvariant(dtype, tile);
+    const uint32_t engine = R.engine == SS_ENGINE_LDS ? (uint32_t)SS_ENGINE_LDS : (uint32_t)SS_ENGINE_REGS;
+    const uint32_t tile = R.tile ? R.tile : 131072u;
+    const BVariant *V = pick_bvariant(dtype, engine, tile);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no batched kernel variant for dtype/tile");
     int occ = 0;
@@ -445,7 +557,8 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
                    nb4 = std::min<uint32_t>((B.num + 3) / 4, 2048u);
     if (levels < 1)
         levels = 1;
-    Gm.search = B.num < (tile == 131072u ? kSearchMaxBig : kSearchMaxSmall) ? 1u : 0u;
+    // (the LDS-tile kernel keeps its table small: its occupancy is bound by LDS)
+    Gm.search = B.num < (engine == SS_ENGINE_LDS ? 1024u : tile == 131072u ? kSearchMaxBig : kSearchMaxSmall);
     for (uint32_t level = 0; level < levels; level++) {
         Gm.level = level;
         if (level == 0)
@@ -666,22 +779,29 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
     if (((uintptr_t)d_splits % 8) || ((uintptr_t)d_pivots % 8))
         return fail_msg(SS_EINVAL, "pivots and splits must be 8-byte aligned");
     Resolved R;
-    int rc = resolve_params(p, dtype, &R);
+    int rc = resolve_params(p, dtype, &R, batched_auto_engine(dtype));
     if (rc)
         return rc;
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
-    if (R.engine != SS_ENGINE_REGS)
-        return fail_msg(SS_EUNSUPPORTED, "batched partition uses the register engine");
+    if (R.engine == SS_ENGINE_REGS2)
+        return fail_msg(SS_EUNSUPPORTED, "batched partition uses the single-buffer register or the LDS engine");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
         return fail_device(e, "hipGetDevice");
-    // size classes: the installed tuning unless the call fixes the geometry
+    // size classes: the installed tuning (measured on the register engine) unless
+    // the call fixes the engine or the geometry
     BatchClasses BC = batched_default_classes(R);
-    if (!(p && (p->b || p->tile_bytes)))
+    if (!(p && (p->b || p->tile_bytes || p->engine)) && batched_has_tuning(dev, dtype)) {
+        Resolved Rr;
+        if ((rc = resolve_params(p, dtype, &Rr, SS_ENGINE_REGS)))
+            return rc;
+        R = Rr;
+        BC = batched_default_classes(R);
         batched_installed_classes(dev, dtype, R, &BC);
+    }
     // Items (groups) per array at any level: at most len / (group elements) + 3.
     uint64_t max_len[kMaxClasses] = {0};
     uint64_t items_cap = 64;
@@ -808,6 +928,22 @@ __global__ void __launch_bounds__(256) k_tune_fill(char *base, uint64_t n, int w
 }
 
 }  // namespace
+
+bool batched_has_tuning(int dev, int dtype)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tuned.count(std::make_pair(dev, dtype)) != 0;
+}
+
+// Default group body of the batched calls: the register engine with 128 KiB
+// groups for every key width.  (The LDS-tile body, which is faster for a
+// single u32 array, measured slower here: inside the quicksort its 32 KiB
+// groups add partition levels and its register use limits occupancy.)
+uint32_t batched_auto_engine(int dtype)
+{
+    (void)dtype;
+    return SS_ENGINE_REGS;
+}
 
 void batched_installed_classes(int dev, int dtype, const Resolved &R, BatchClasses *C)
 {

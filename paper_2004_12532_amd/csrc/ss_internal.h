@@ -129,6 +129,8 @@ int batched_graph(int dev, char *base, int dtype, const Resolved &R, const Batch
 void batched_graphs_forget(const void *state);
 BatchClasses batched_default_classes(const Resolved &R);
 void batched_installed_classes(int dev, int dtype, const Resolved &R, BatchClasses *C);
+bool batched_has_tuning(int dev, int dtype);
+uint32_t batched_auto_engine(int dtype);
 int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B, uint32_t levels,
                  hipStream_t st, uint64_t *d_splits, uint32_t *launches);
 

@@ -498,12 +498,12 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
     if (rc)
         return rc;
     Resolved R;
-    if ((rc = resolve_params(p, dtype, &R)))
+    if ((rc = resolve_params(p, dtype, &R, batched_auto_engine(dtype))))
         return rc;
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the batched Smoothed Striding partition");
-    if (R.engine != SS_ENGINE_REGS)
-        return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the register engine");
+    if (R.engine == SS_ENGINE_REGS2)
+        return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the single-buffer register or the LDS engine");
     if ((rc = check_lines(n, R)))
         return rc;
     hipStream_t st = (hipStream_t)stream;

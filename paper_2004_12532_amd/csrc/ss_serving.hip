@@ -267,7 +267,7 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
     s->capacity = capacity;
     s->st = (hipStream_t)stream;
     hipError_t e;
-    if ((rc = resolve_params(nullptr, dtype, &s->R))) {
+    if ((rc = resolve_params(nullptr, dtype, &s->R, batched_auto_engine(dtype)))) {
         delete s;
         return rc;
     }

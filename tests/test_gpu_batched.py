@@ -203,3 +203,17 @@ def test_autotune_installs_a_table_that_keeps_parity(ss, kind):
         _check(data, out, offsets, pivots, splits)
     finally:
         ss.set_batched_tuning(kind, None)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+@pytest.mark.parametrize("tile", [32768, 65536])
+def test_batched_lds_engine_parity(ss, kind, tile):
+    """The LDS-tile group body gives the register body's bytes (same stable partition of every group)."""
+    lengths = np.concatenate([[0, 1, 2, 65, 4095, 16385],
+                              workloads.lognormal_lengths(150, 21, median_log2=12.0, sigma_log2=1.5, lo=1,
+                                                          hi=1 << 18)]).astype(np.int64)
+    data, offsets, pivots = _batch(kind, lengths, 17)
+    out, splits, _ = _run_batched(ss, data, offsets, pivots, engine="lds", tile_bytes=tile)
+    _check(data, out, offsets, pivots, splits)
+    out_r, splits_r, _ = _run_batched(ss, data, offsets, pivots, engine="regs", tile_bytes=tile)
+    assert np.array_equal(splits, splits_r) and np.array_equal(out, out_r)

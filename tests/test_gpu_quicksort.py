@@ -117,3 +117,20 @@ def test_sort_segments_and_median3(ss, kind):
             assert np.array_equal(seg, ref)
     with pytest.raises(ss.SSError):
         ss.sort_segments(t, [0], [cap + 1])
+
+
+@pytest.mark.parametrize("kind", ["u32", "kv"])
+def test_quicksort_lds_engine(ss, kind):
+    a0 = gen(kind, 300001, 77)
+    t = to_device(a0)
+    ss.quicksort(t, engine="lds")
+    out = to_host(t, a0)
+    ref = a0.copy()
+    oracle.quicksort(ref)
+    if a0.ndim == 2:
+        assert np.array_equal(out[:, 0], ref[:, 0])
+        o = out[np.lexsort((out[:, 1], out[:, 0]))]
+        r = ref[np.lexsort((ref[:, 1], ref[:, 0]))]
+        assert np.array_equal(o, r)
+    else:
+        assert np.array_equal(out, ref)
