@@ -85,7 +85,18 @@ def cpu_baseline(seconds_budget: float = 12.0):
     t = sorted(times)[len(times) // 2]
     return {"value": round(2 * n * 8 / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": "serial two-pointer partition of 2^27 i.i.d. uint64 keys (same generator) at the "
-                      "median, %d runs, median time %.3f s, 1 thread" % (len(times), t)}
+                      "median, %d runs, median time %.3f s, 1 thread" % (len(times), t),
+            "host_cpu": _host_cpu(), "host_threads": os.cpu_count()}
+
+
+def _host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _exit_multi_gpu(gpus):
