@@ -84,3 +84,16 @@ def test_line_count_limit_rejected_before_device_work():
     rc = ss.lib.ss_partition_ex(ctypes.c_void_p(0x1000), (1 << 36) + 5, ss.SS_U32, 5, ctypes.byref(p), None, None,
                                 ctypes.byref(split), None)
     assert rc == -1 and b"lines" in ss.lib.ss_last_error()
+
+
+def test_server_engine_argument_validation_without_device():
+    import paper_2004_12532_amd as ss
+    L = ss.lib
+    out = ctypes.c_void_p(1)
+    assert L.ss_server_create(None, 10, ss.SS_KV16, 4, 4, None, ctypes.byref(out)) == -1        # null base
+    assert L.ss_server_create(ctypes.c_void_p(0x1008), 10, ss.SS_KV16, 4, 4, None, ctypes.byref(out)) == -1
+    assert L.ss_server_create(ctypes.c_void_p(0x1000), 10, ss.SS_KV16, 0, 4, None, ctypes.byref(out)) == -1
+    assert out.value is None                                  # cleared on error
+    assert L.ss_server_submit(None, 0, 0, 1, 0, 0) == -1
+    assert L.ss_server_tick(None, 1) == -1
+    assert ss.server_job_aux_bytes(ss.SS_KV16, 1, 1 << 20) > ss.server_job_aux_bytes(ss.SS_KV16, 0, 1 << 20)

@@ -69,3 +69,41 @@ def test_serving_realtime_arrivals_and_budget(ss):
         assert job.done >= job.admitted >= job.arrival
         _check_job(job, srv.outputs[job.job_id])
     assert srv.arena.used == 0
+
+
+def test_engine_direct_jobs_and_capacity_flag(ss):
+    """The engine through its C ABI: partition splits against the oracle, trivial
+    jobs done at once, and a full segment list reported by the status flags."""
+    import torch
+    import workloads
+    n_jobs, L = 6, 5000
+    data = workloads.records_kv(n_jobs * L, 4)
+    t = torch.from_numpy(data.view(np.int64).copy()).cuda()
+    eng = ss.ServerEngine(t, max_jobs=16, max_segments=4)
+    pivots = [int(workloads.pivot_at_quantile_np(data[k * L:(k + 1) * L], q))
+              for k, q in enumerate((0.1, 0.3, 0.5, 0.7, 0.9, 0.5))]
+    for k in range(4):
+        eng.submit(k, k * L, L, 0, pivots[k])
+    eng.submit(10, 0, 0, 0, 0)          # empty partition: done at once
+    eng.submit(11, 0, 1, 1, 0)          # one-record sort: done at once
+    eng.tick(L)
+    eng.wait(0)
+    assert eng.done(10)[0] and eng.done(11)[0]
+    out = t.cpu().numpy().view(np.uint64)
+    for k in range(4):
+        fin, split = eng.done(k)
+        assert fin
+        ref = data[k * L:(k + 1) * L].copy()
+        assert split == oracle.partition(ref, pivots[k])
+        gl, gr = oracle.sorted_sides(out[k * L:(k + 1) * L], split)
+        rl, rr = oracle.sorted_sides(ref, split)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+    assert eng.status() == 0
+    # five segments into a list of four: the fifth is refused and flagged, the others finish
+    for k in range(5):
+        eng.submit(k, (k % n_jobs) * L, L, 0, pivots[k % n_jobs])
+    eng.tick(L)
+    eng.wait(0)
+    assert eng.status() & 1
+    assert sum(eng.done(k)[0] for k in range(5)) == 4
+    eng.close()
