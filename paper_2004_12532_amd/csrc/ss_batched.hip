@@ -98,26 +98,35 @@ __global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
 constexpr int kScanNT = 1024, kScanPer = 8, kScanChunk = kScanNT * kScanPer;
 
 struct ScanSmem {
-    uint64_t tile[kScanChunk];
     uint64_t wsum[kScanNT / 64], wopen[kScanNT / 64];
 };
 
 // Exclusive scan of g over all arrays by one workgroup of kScanNT threads.
+// Each thread takes kScanPer consecutive entries of a chunk with two 16-byte
+// loads and writes their kScanPer first-item offsets as four 16-byte stores,
+// so a wavefront reads 2 KiB and writes 4 KiB contiguously per chunk.
 __device__ void scan_groups(const BatchState &B, ScanSmem &S)
 {
+    static_assert(kScanPer == 8, "two 16-byte loads of g per thread");
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     uint64_t carry = 0, ocarry = 0;
     const uint32_t num = bnum(B);
     for (uint32_t c0 = 0; c0 < num; c0 += kScanChunk) {
-        const uint32_t m = num - c0 < (uint32_t)kScanChunk ? num - c0 : (uint32_t)kScanChunk;
-        for (uint32_t j = tid; j < m; j += kScanNT)
-            S.tile[j] = B.g[c0 + j];
-        __syncthreads();
-        uint64_t v[kScanPer], s = 0, open = 0;
+        const uint32_t j0 = c0 + (uint32_t)tid * kScanPer;
+        uint32_t v[kScanPer];
+        if (j0 + kScanPer <= num) {
+            const v4u a = *reinterpret_cast<const v4u *>(B.g + j0);
+            const v4u b = *reinterpret_cast<const v4u *>(B.g + j0 + 4);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+#pragma unroll
+            for (int r = 0; r < kScanPer; r++)
+                v[r] = j0 + r < num ? B.g[j0 + r] : 0u;
+        }
+        uint64_t s = 0, open = 0;
 #pragma unroll
         for (int r = 0; r < kScanPer; r++) {
-            const uint32_t j = tid * kScanPer + r;
-            v[r] = j < m ? S.tile[j] : 0;
             s += v[r];
             open += v[r] != 0;
         }
@@ -143,19 +152,26 @@ __device__ void scan_groups(const BatchState &B, ScanSmem &S)
             otot += S.wopen[w];
         }
         uint64_t run = off + inc - s;
+        uint64_t f[kScanPer];
 #pragma unroll
         for (int r = 0; r < kScanPer; r++) {
-            const uint32_t j = tid * kScanPer + r;
-            if (j < m)
-                S.tile[j] = run;
+            f[r] = run;
             run += v[r];
         }
-        __syncthreads();
-        for (uint32_t j = tid; j < m; j += kScanNT)
-            B.first[c0 + j] = S.tile[j];
+        if (j0 + kScanPer <= num) {
+            typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+            for (int r = 0; r < kScanPer; r += 2)
+                *reinterpret_cast<u64x2 *>(B.first + j0 + r) = u64x2{f[r], f[r + 1]};
+        } else {
+#pragma unroll
+            for (int r = 0; r < kScanPer; r++)
+                if (j0 + r < num)
+                    B.first[j0 + r] = f[r];
+        }
         carry += tot;
         ocarry += otot;
-        __syncthreads();  // tile and wsum are rewritten by the next chunk
+        __syncthreads();  // wsum is rewritten by the next chunk
     }
     if (tid == 0) {
         B.first[num] = carry;
@@ -577,7 +593,7 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
     }
     Gm.level = levels;
     hipLaunchKernelGGL(k_bstep, dim3(nb4), dim3(256), 0, st, B, Gm);
-    const uint32_t ncl = B.num < 4096u ? B.num : 4096u;
+    const uint32_t ncl = B.num < (uint32_t)cus ? B.num : (uint32_t)cus;  // open arrays are rare: one pass per CU
     switch (dtype) {
     case SS_U32: hipLaunchKernelGGL(k_bcleanup<uint32_t>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
     case SS_U64: hipLaunchKernelGGL(k_bcleanup<uint64_t>, dim3(ncl), dim3(1024), 0, st, B, Gm); break;
