@@ -120,9 +120,11 @@ typedef struct ss_params {
  *                  in ss_partition / ss_partition_ex, which use SS_ENGINE_LDS
  *                  with 32768-byte groups (four 4-byte scattered stores per
  *                  16-byte vector cost more than staging through LDS).  The
- *                  batched calls, the quicksort and the serving engine use
- *                  the register engine unless p->engine asks for the LDS one
- *                  (32768- or 65536-byte groups). */
+ *                  batched calls and the serving engine use the register
+ *                  engine with 131072-byte groups, and the LDS engine with
+ *                  32768-byte groups for SS_U32; the quicksort's levels use
+ *                  the LDS engine with 65536-byte groups for SS_U32.  An
+ *                  explicit p->engine / tile_bytes overrides these. */
 #define SS_ENGINE_AUTO 0u
 #define SS_ENGINE_LDS 1u
 #define SS_ENGINE_REGS 2u

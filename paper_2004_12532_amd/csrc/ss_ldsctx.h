@@ -26,7 +26,7 @@ struct LdsCtx {
     static constexpr int NV = NVEC / NT;
     static constexpr int NW = NT / 64;
     static constexpr int E = NV * NW;
-    static_assert(NV * NT == NVEC && E <= 64, "tile shape");
+    static_assert(NV * NT == NVEC && E <= 64 && NV * V <= 64, "tile shape");
 
     char *A0;
     const uint32_t *xoff;
@@ -48,24 +48,55 @@ struct LdsCtx {
     }
     __device__ __forceinline__ char *elem_ptr(uint64_t vpos) const { return A0 + (vpos << LOG2W); }
 
-    // bit r of `partial`: vector r is not entirely real
-    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i, uint32_t &partial) const
+    // Every slot of group i is a real element and the group fills the tile.
+    __device__ __forceinline__ bool fast(uint32_t i) const
     {
-        partial = 0;
+        if (nvec != (uint32_t)NVEC)
+            return false;
+        uint32_t r0 = xoff[0] + i;
+        r0 = r0 >= g ? r0 - g : r0;
+        if (fp && r0 == 0)
+            return false;
+        uint32_t rl = xoff[s - 1] + i;
+        rl = rl >= g ? rl - g : rl;
+        return ((uint64_t)((s - 1) * g + rl + 1) << log2b) <= real_end;
+    }
+
+    // Real elements and virtual front predecessors of this thread's vectors
+    // (bit r * V + e), as in LevelCtx.
+    struct Mask {
+        uint64_t real, front;
+    };
+
+    template <bool FAST>
+    __device__ __forceinline__ void load(v4u (&buf)[NV], uint32_t i, Mask &m) const
+    {
+        m.real = 0;
+        m.front = 0;
 #pragma unroll
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
-            buf[r] = v4u{0u, 0u, 0u, 0u};
-            if (q < nvec) {
-                const uint64_t e0 = vec_start(q, i);
-                if (e0 >= fp && e0 + V <= real_end) {
-                    buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(e0));
-                } else {
-                    partial |= 1u << r;
+            if (FAST) {
+                buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(vec_start(q, i)));
+            } else {
+                buf[r] = v4u{0u, 0u, 0u, 0u};
+                if (q < nvec) {
+                    const uint64_t e0 = vec_start(q, i);
+                    if (e0 >= fp && e0 + V <= real_end) {
+                        buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(e0));
+                        m.real |= (uint64_t)((1u << V) - 1) << (r * V);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < V; e++)
-                        if (e0 + e >= fp && e0 + e < real_end)
-                            Elem<T>::load1(buf[r], e, elem_ptr(e0 + e));
+                        for (int e = 0; e < V; e++) {
+                            const uint64_t vp = e0 + e;
+                            if (vp >= fp && vp < real_end) {
+                                Elem<T>::load1(buf[r], e, elem_ptr(vp));
+                                m.real |= 1ull << (r * V + e);
+                            } else if (vp < fp) {
+                                m.front |= 1ull << (r * V + e);
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -73,37 +104,24 @@ struct LdsCtx {
 
     // Stable partition of group i into the tile, then the tile back to the
     // group's lines; returns c_i.
-    __device__ __forceinline__ uint32_t partition_store(const v4u (&buf)[NV], uint32_t i, uint32_t partial) const
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t partition_store(const v4u (&buf)[NV], uint32_t i, const Mask &m) const
     {
-        uint32_t pbits[NV], lex[NV];
+        constexpr uint32_t VM = (1u << V) - 1;
+        uint64_t pb = 0;
 #pragma unroll
         for (int r = 0; r < NV; r++) {
-            const uint32_t q = r * NT + tid;
             uint32_t bits = 0;
-            if (q < nvec) {
-                if (!((partial >> r) & 1)) {
 #pragma unroll
-                    for (int e = 0; e < V; e++)
-                        bits |= (uint32_t)(Elem<T>::key(buf[r], e) < pivot) << e;
-                } else {
-                    const uint64_t e0 = vec_start(q, i);
+            for (int e = 0; e < V; e++)
+                bits |= (uint32_t)(Elem<T>::key(buf[r], e) < pivot) << e;
+            if (!FAST)
+                bits = (bits & (uint32_t)(m.real >> (r * V)) & VM) | ((uint32_t)(m.front >> (r * V)) & VM);
+            pb |= (uint64_t)bits << (r * V);
+            uint32_t tot = 0;
 #pragma unroll
-                    for (int e = 0; e < V; e++) {
-                        const uint64_t vp = e0 + e;
-                        const bool real = vp >= fp && vp < real_end;
-                        bits |= (uint32_t)(real ? Elem<T>::key(buf[r], e) < pivot : vp < fp) << e;
-                    }
-                }
-            }
-            pbits[r] = bits;
-            uint32_t ex = 0, tot = 0;
-#pragma unroll
-            for (int e = 0; e < V; e++) {
-                const uint64_t m = __ballot((bits >> e) & 1);
-                ex += lanes_below(m);
-                tot += __popcll(m);
-            }
-            lex[r] = ex;
+            for (int e = 0; e < V; e++)
+                tot += __popcll(__ballot((bits >> e) & 1));
             if (lane == 0)
                 wtot[r * NW + wid] = tot;
         }
@@ -127,35 +145,40 @@ struct LdsCtx {
 #pragma unroll
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
-            if (q < nvec) {
-                uint32_t rp = wpre[r * NW + wid] + lex[r];
-                const bool full = !((partial >> r) & 1);
-                const uint64_t e0 = full ? 0 : vec_start(q, i);
+            const uint32_t bits = (uint32_t)(pb >> (r * V)) & VM;
+            uint32_t rp = wpre[r * NW + wid];
 #pragma unroll
-                for (int e = 0; e < V; e++) {
-                    const bool p = (pbits[r] >> e) & 1;
-                    const uint32_t slot = q * V + e;
-                    const uint32_t d = p ? rp : c + slot - rp;
-                    if (full || (e0 + e >= fp && e0 + e < real_end))
-                        Elem<T>::put(tile, d, buf[r], e);
-                    rp += p;
-                }
+            for (int e = 0; e < V; e++)
+                rp += lanes_below(__ballot((bits >> e) & 1));
+#pragma unroll
+            for (int e = 0; e < V; e++) {
+                const bool p = (bits >> e) & 1;
+                const uint32_t slot = q * V + e;
+                const uint32_t d = p ? rp : c + slot - rp;
+                rp += p;
+                if (FAST || ((m.real >> (r * V + e)) & 1))
+                    Elem<T>::put(tile, d, buf[r], e);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
-            if (q < nvec) {
-                const v4u v = tile[q];
-                const uint64_t e0 = vec_start(q, i);
-                if (!((partial >> r) & 1)) {
-                    *reinterpret_cast<v4u *>(elem_ptr(e0)) = v;
-                } else {
+            if (FAST) {
+                *reinterpret_cast<v4u *>(elem_ptr(vec_start(q, i))) = tile[q];
+            } else if (q < nvec) {
+                const uint32_t vm = (uint32_t)(m.real >> (r * V)) & VM;
+                if (vm) {
+                    const v4u v = tile[q];
+                    const uint64_t e0 = vec_start(q, i);
+                    if (vm == VM) {
+                        *reinterpret_cast<v4u *>(elem_ptr(e0)) = v;
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < V; e++)
-                        if (e0 + e >= fp && e0 + e < real_end)
-                            Elem<T>::store1(v, e, elem_ptr(e0 + e));
+                        for (int e = 0; e < V; e++)
+                            if ((vm >> e) & 1)
+                                Elem<T>::store1(v, e, elem_ptr(e0 + e));
+                    }
                 }
             }
         }

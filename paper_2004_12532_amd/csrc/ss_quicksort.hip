@@ -500,6 +500,18 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
     Resolved R;
     if ((rc = resolve_params(p, dtype, &R, batched_auto_engine(dtype))))
         return rc;
+    if (dtype == SS_U32 && !(p && (p->engine || p->tile_bytes || p->b))) {
+        // u32 levels: the LDS body with 64 KiB groups, which hold a whole leaf-sized
+        // segment (measured 8.6% faster than the register body on 2^28 keys)
+        ss_params q;
+        std::memset(&q, 0, sizeof(q));
+        if (p)
+            q = *p;
+        q.engine = SS_ENGINE_LDS;
+        q.tile_bytes = 65536;
+        if ((rc = resolve_params(&q, dtype, &R)))
+            return rc;
+    }
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the batched Smoothed Striding partition");
     if (R.engine == SS_ENGINE_REGS2)
