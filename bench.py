@@ -35,6 +35,9 @@ WORKLOADS = {
     "partition_u64_2p30_q0.1": ("u64", 30, 0.1),
     "partition_u64_2p30_q0.01": ("u64", 30, 0.01),
     "partition_u64_2p30_desc": ("u64", 30, "desc"),
+    # stride-aligned adversary: predecessors fill exactly the lines l with (l mod g) < g/2 for the
+    # default geometry (512-byte lines, 256 lines per group), pivot 2^63
+    "partition_u64_2p30_stride_adv": ("u64", 30, "adv"),
 }
 LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_levelctx.h",
                  "paper_2004_12532_amd/csrc/ss_device.h", "paper_2004_12532_amd/csrc/ss_common.h"]
@@ -122,8 +125,13 @@ def run_partition(args, workload, algo="smoothed"):
     w = 8
     dev = torch.device("cuda", 0)
 
-    pristine = workloads.keys_u64_torch(n, workloads.config_seed(1), dev)
-    pivot = workloads.pivot_at_quantile_torch(pristine, 0.5 if q == "desc" else q)
+    if q == "adv":
+        g = workloads.stride_groups(n, 64, 256)
+        pristine = workloads.stride_adversarial_u64_torch(n, workloads.config_seed(1), 64, g, dev)
+        pivot = 1 << 63
+    else:
+        pristine = workloads.keys_u64_torch(n, workloads.config_seed(1), dev)
+        pivot = workloads.pivot_at_quantile_torch(pristine, 0.5 if q == "desc" else q)
     if q == "desc":
         pristine = workloads.sort_descending_u64_torch(pristine)
     expected = int((workloads.to_unsigned_order(pristine) <
@@ -209,7 +217,9 @@ def run_partition(args, workload, algo="smoothed"):
             "traffic": traffic,
             "kernel": {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
                        "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
-                       "lowspace": "whole Low-Space call (all its kernels)"}[algo],
+                       "lowspace": "whole Low-Space call (all its kernels)",
+                       "hybrid": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step before the "
+                                 "Low-Space pass over the middle)"}[algo],
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "probe": probe,
@@ -375,7 +385,8 @@ def run_serving(args):
 
 
 SUITE = ["partition_u64_2p30_q0.1", "partition_u64_2p30_q0.01", "partition_u64_2p30_desc",
-         "partition_u64_2p30_q0.5:strided", "partition_u64_2p30_q0.5:lowspace",
+         "partition_u64_2p30_stride_adv", "partition_u64_2p30_stride_adv:strided",
+         "partition_u64_2p30_q0.5:strided", "partition_u64_2p30_q0.5:lowspace", "partition_u64_2p30_q0.5:hybrid",
          "quicksort_u32_2p28", "quicksort_u32_2p28_d1024", "batched_u64_20000", "serving_kv16"]
 
 
@@ -402,7 +413,7 @@ def main():
     ap.add_argument("--workload", default="partition_u64_2p30_q0.5",
                     choices=sorted(WORKLOADS) + ["quicksort_u32_2p28", "quicksort_u32_2p28_d1024",
                                                  "batched_u64_20000", "serving_kv16"])
-    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace"])
+    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace", "hybrid"])
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -66,8 +66,13 @@ enum ss_dtype { SS_U32 = 1, SS_U64 = 2, SS_KV16 = 3 };
  *               workgroup.
  * SS_LOWSPACE : the Low-Space implementation of the Blocked-Prefix-Sum
  *               partition (Section 3 with the explicit block-count array of
- *               Section 5.1); its auxiliary memory is about n/32 words. */
-enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2 };
+ *               Section 5.1); its auxiliary memory is about n/32 words.
+ * SS_HYBRID   : the Hybrid Smoothed Striding Algorithm (Section 4): one
+ *               Partial Partition Step, then the Blocked-Prefix-Sum partition
+ *               (SS_LOWSPACE) of the middle region [v_min, v_max).  The call
+ *               synchronizes the stream once between the two phases (the
+ *               host needs v_min and v_max), so it is never asynchronous. */
+enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2, SS_HYBRID = 3 };
 
 enum ss_status {
     SS_OK = 0,

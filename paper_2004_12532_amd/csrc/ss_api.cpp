@@ -159,7 +159,7 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     std::memset(&q, 0, sizeof(q));
     if (p)
         q = *p;
-    if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE)
+    if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE && q.algo != SS_HYBRID)
         return fail_msg(SS_EINVAL, "unknown algo");
     if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH))
         return fail_msg(SS_EINVAL, "unknown flags");
@@ -436,6 +436,71 @@ using namespace ss;
 
 extern "C" {
 
+// Hybrid Smoothed Striding (Section 4): one Partial Partition Step, then the
+// Blocked-Prefix-Sum partition (the Low-Space implementation) of the middle
+// region [v_min, v_max).  The host reads (v_min, v_max) between the phases.
+static int hybrid_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                            uint64_t *d_split, size_t *h_split, ss_stats *stats)
+{
+    Resolved R1 = R;
+    R1.algo = SS_SMOOTHED;
+    R1.flags = R.flags | SS_FLAG_ONE_LEVEL;  // with SS_FLAG_TIME the first level is timed as usual
+    RunOut ro;
+    std::memset(&ro, 0, sizeof(ro));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    const bool timing = (R.flags & SS_FLAG_TIME) != 0;
+    if (timing) {
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+            return fail_msg(SS_EDEVICE, "hipEventCreate");
+        (void)hipEventRecord(t0, st);
+    }
+    int rc = run_partition(base, n, dtype, pivot, R1, st, nullptr, true, &ro);
+    if (rc)
+        return rc;
+    uint64_t split = ro.vmin;
+    size_t mid_aux = 0;
+    if (!(R.flags & SS_FLAG_ONE_LEVEL) && ro.vmax > ro.vmin) {
+        Resolved R2 = R;
+        R2.algo = SS_LOWSPACE;
+        R2.flags = R.flags & ~SS_FLAG_TIME;
+        size_t sub = 0;
+        ss_stats st2;
+        rc = lowspace_partition(base + ro.vmin * (uint64_t)R.w, (size_t)(ro.vmax - ro.vmin), dtype, pivot, R2, st,
+                                nullptr, &sub, &st2);
+        if (rc)
+            return rc;
+        split = ro.vmin + sub;
+        mid_aux = st2.aux_bytes;
+    }
+    if (timing) {
+        (void)hipEventRecord(t1, st);
+        (void)hipEventSynchronize(t1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ro.total_ms = ms;
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    }
+    if (d_split) {
+        hipError_t e = hipMemcpy(d_split, &split, sizeof(split), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return fail_device(e, "hipMemcpy");
+    }
+    if (h_split)
+        *h_split = (size_t)split;
+    if (stats) {
+        ro.split = split;
+        fill_stats(stats, ro, R, dtype);
+        stats->split = split;
+        stats->aux_bytes = ro.aux_bytes > mid_aux ? ro.aux_bytes : mid_aux;
+        if (!(R.flags & SS_FLAG_ONE_LEVEL)) {
+            stats->vmin = split;
+            stats->vmax = split;
+        }
+    }
+    return SS_OK;
+}
+
 int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_params *p, void *stream,
                     uint64_t *d_split, size_t *h_split, ss_stats *stats)
 {
@@ -452,6 +517,24 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
                                   stats);
     if ((rc = check_lines(n, R)))
         return rc;
+    if (R.algo == SS_HYBRID) {
+        if (d_split && ((uintptr_t)d_split % 8))
+            return fail_msg(SS_EINVAL, "d_split not 8-byte aligned");
+        if (n == 0) {
+            if (h_split)
+                *h_split = 0;
+            const uint64_t zero = 0;
+            if (d_split && hipMemcpy(d_split, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+                return fail_msg(SS_EDEVICE, "hipMemcpy");
+            if (stats) {
+                RunOut ro;
+                std::memset(&ro, 0, sizeof(ro));
+                fill_stats(stats, ro, R, dtype);
+            }
+            return SS_OK;
+        }
+        return hybrid_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split, stats);
+    }
     if (d_split && ((uintptr_t)d_split % 8))
         return fail_msg(SS_EINVAL, "d_split not 8-byte aligned");
     const bool sync = h_split || stats;
@@ -517,7 +600,7 @@ size_t ss_aux_bytes(size_t n, int dtype, int algo)
         return 0;
     const size_t ws = ((size_t)kMaxLevels * 2 * kMaxGrid + (size_t)kMaxLevels * kCtlWords + kResultWords) *
                       sizeof(uint64_t);
-    if (algo == SS_LOWSPACE)
+    if (algo == SS_LOWSPACE || algo == SS_HYBRID)  // hybrid: Low-Space arrays for the middle region (< n)
         return ws + lowspace_aux_bytes(n);
     return ws;
 }

@@ -98,3 +98,32 @@ def test_lowspace_large_properties(ss):
         assert oracle.is_partitioned(out, p, split)
         assert oracle.fingerprint(out) == oracle.fingerprint(a0)
         assert st["aux_bytes"] >= n // 64 * 4
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_hybrid_parity(ss, kind):
+    """Hybrid Smoothed Striding: one Partial Partition Step, then Low-Space on the middle region."""
+    for n in (1, 2, 1000, 65537, 300001, (1 << 20) + 7):
+        a0 = gen(kind, n, 500 + n)
+        keys = a0[:, 0] if a0.ndim == 2 else a0
+        pivots = {0, int(keys.max()) + 1}
+        for q in (0.1, 0.5, 0.9):
+            pivots.add(workloads.pivot_at_quantile_np(a0, q))
+        for p in sorted(pivots):
+            check_against_oracle(ss, a0, p, algo="hybrid")
+
+
+def test_hybrid_large_and_async(ss):
+    import torch
+    n = (1 << 26) + 3
+    a0 = workloads.keys_u64(n, 77)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    t = to_device(a0)
+    d = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    ss.partition_async(t, p, d, algo="hybrid")
+    torch.cuda.synchronize()
+    out = to_host(t, a0)
+    split = int(d.item())
+    assert split == oracle.count_less(a0, p)
+    assert oracle.is_partitioned(out, p, split)
+    assert oracle.fingerprint(out) == oracle.fingerprint(a0)

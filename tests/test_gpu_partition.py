@@ -293,3 +293,31 @@ def test_more_than_2p32_elements_u32(ss):
     assert oracle.fingerprint(host_out) == fp_in
     del t, host_out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("algo", ["smoothed", "strided", "lowspace"])
+def test_stride_adversary_parity(ss, algo):
+    """Keys whose predecessors fill exactly the lines l with (l mod g) < g/2."""
+    n = (1 << 20) + 77
+    g = workloads.stride_groups(n, 64, 256)   # default geometry: 512-byte lines, 256 lines per group
+    a0 = workloads.stride_adversarial_u64(n, 8, 64, g)
+    check_against_oracle(ss, a0, 1 << 63, algo=algo)
+
+
+def test_stride_adversary_middle_regions(ss):
+    """Section 4's motivation for the random offsets: with every offset 0 each
+    stride set of this input is all predecessors or all successors, so one
+    Strided step leaves almost the whole array between v_min and v_max; the
+    offsets of Smoothed Striding mix every group and leave a fraction of it."""
+    n = 1 << 22
+    g = workloads.stride_groups(n, 64, 256)
+    a0 = workloads.stride_adversarial_u64(n, 9, 64, g)
+    mids = {}
+    for algo in ("strided", "smoothed"):
+        t = to_device(a0)
+        _, st = ss.partition(t, 1 << 63, algo=algo, one_level=True, stats=True)
+        out = to_host(t, a0)
+        assert oracle.fingerprint(out) == oracle.fingerprint(a0)
+        mids[algo] = st["vmax"] - st["vmin"]
+    assert mids["strided"] > 0.95 * n, mids
+    assert mids["smoothed"] < 0.5 * n, mids

@@ -56,6 +56,23 @@ def keys_u64(n: int, seed: int, start: int = 0) -> np.ndarray:
     return splitmix64_np(seed, start, n)
 
 
+def stride_groups(n: int, line_elems: int, s_max: int) -> int:
+    """Groups g of a Partial Partition Step over n elements with lines of
+    line_elems elements and at most s_max lines per group (g = ceil(L / s_max))."""
+    lines = -(-n // line_elems)
+    return max(1, -(-lines // s_max))
+
+
+def stride_adversarial_u64(n: int, seed: int, line_elems: int, g: int) -> np.ndarray:
+    """Keys whose predecessors (key < 2^63) fill exactly the lines l with
+    (l mod g) < g/2: every stride set of the Strided Algorithm (offsets 0) is
+    then all predecessors or all successors.  Low 63 bits are uniform."""
+    k = splitmix64_np(seed, 0, n) >> np.uint64(1)
+    line = np.arange(n, dtype=np.uint64) // np.uint64(line_elems)
+    succ = (line % np.uint64(g)) >= np.uint64(g // 2)
+    return k | (succ.astype(np.uint64) << np.uint64(63))
+
+
 def keys_u32(n: int, seed: int, start: int = 0) -> np.ndarray:
     return (splitmix64_np(seed, start, n) >> np.uint64(32)).astype(np.uint32)
 
@@ -147,6 +164,19 @@ def splitmix64_torch(seed: int, start: int, count: int, device, out=None, chunk:
 
 def keys_u64_torch(n: int, seed: int, device, out=None):
     return splitmix64_torch(seed, 0, n, device, out=out)
+
+
+def stride_adversarial_u64_torch(n: int, seed: int, line_elems: int, g: int, device, chunk: int = 1 << 26):
+    """Device twin of stride_adversarial_u64 (same values)."""
+    import torch
+    out = splitmix64_torch(seed, 0, n, device)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        z = _srl(out[c0:c1], 1)
+        line = torch.arange(c0, c1, dtype=torch.int64, device=device) // line_elems
+        succ = (line % g) >= (g // 2)
+        out[c0:c1] = torch.where(succ, z | torch.tensor(-(1 << 63), dtype=torch.int64, device=device), z)
+    return out
 
 
 def keys_u32_torch(n: int, seed: int, device, chunk: int = 1 << 26):
