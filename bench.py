@@ -219,7 +219,9 @@ def run_partition(args, workload, algo="smoothed"):
                        "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
                        "lowspace": "whole Low-Space call (all its kernels)",
                        "hybrid": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step before the "
-                                 "Low-Space pass over the middle)"}[algo],
+                                 "Low-Space pass over the middle)",
+                       "mediumspace": "whole Medium-Space call (all its kernels and the copy back)",
+                       "highspace": "whole High-Space call (all its kernels and the copy back)"}[algo],
             "algorithmic_bytes_per_launch": alg_bytes,
         },
         "probe": probe,
@@ -387,6 +389,7 @@ def run_serving(args):
 SUITE = ["partition_u64_2p30_q0.1", "partition_u64_2p30_q0.01", "partition_u64_2p30_desc",
          "partition_u64_2p30_stride_adv", "partition_u64_2p30_stride_adv:strided",
          "partition_u64_2p30_q0.5:strided", "partition_u64_2p30_q0.5:lowspace", "partition_u64_2p30_q0.5:hybrid",
+         "partition_u64_2p30_q0.5:mediumspace", "partition_u64_2p30_q0.5:highspace",
          "quicksort_u32_2p28", "quicksort_u32_2p28_d1024", "batched_u64_20000", "serving_kv16"]
 
 
@@ -413,7 +416,8 @@ def main():
     ap.add_argument("--workload", default="partition_u64_2p30_q0.5",
                     choices=sorted(WORKLOADS) + ["quicksort_u32_2p28", "quicksort_u32_2p28_d1024",
                                                  "batched_u64_20000", "serving_kv16"])
-    ap.add_argument("--algo", default="smoothed", choices=["smoothed", "strided", "lowspace", "hybrid"])
+    ap.add_argument("--algo", default="smoothed",
+                    choices=["smoothed", "strided", "lowspace", "hybrid", "mediumspace", "highspace"])
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -71,8 +71,15 @@ enum ss_dtype { SS_U32 = 1, SS_U64 = 2, SS_KV16 = 3 };
  *               Partial Partition Step, then the Blocked-Prefix-Sum partition
  *               (SS_LOWSPACE) of the middle region [v_min, v_max).  The call
  *               synchronizes the stream once between the two phases (the
- *               host needs v_min and v_max), so it is never asynchronous. */
-enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2, SS_HYBRID = 3 };
+ *               host needs v_min and v_max), so it is never asynchronous.
+ * SS_MEDIUMSPACE, SS_HIGHSPACE : the Medium- and High-Space comparators
+ *               (Section 5.1): the standard parallel partition into an
+ *               n-element output array, copied back.  Medium-Space keeps the
+ *               predecessor prefix only per block of 64 elements (n/64
+ *               words); High-Space also writes every element's prefix into an
+ *               n-word array first.  Not in place: ss_aux_bytes reports the
+ *               extra n elements (and n words). */
+enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2, SS_HYBRID = 3, SS_MEDIUMSPACE = 4, SS_HIGHSPACE = 5 };
 
 enum ss_status {
     SS_OK = 0,

@@ -27,8 +27,9 @@ if not os.path.exists(_SO):
 _lib = ctypes.CDLL(_SO)
 
 SS_U32, SS_U64, SS_KV16 = 1, 2, 3
-SMOOTHED, STRIDED, LOWSPACE, HYBRID = 0, 1, 2, 3
-ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE, "hybrid": HYBRID}
+SMOOTHED, STRIDED, LOWSPACE, HYBRID, MEDIUMSPACE, HIGHSPACE = 0, 1, 2, 3, 4, 5
+ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE, "hybrid": HYBRID,
+         "mediumspace": MEDIUMSPACE, "highspace": HIGHSPACE}
 FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH = 1, 2, 4, 8, 16
 MAX_LEVELS = 32
 STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",

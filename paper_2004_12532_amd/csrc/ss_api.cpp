@@ -159,7 +159,7 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     std::memset(&q, 0, sizeof(q));
     if (p)
         q = *p;
-    if (q.algo != SS_SMOOTHED && q.algo != SS_STRIDED && q.algo != SS_LOWSPACE && q.algo != SS_HYBRID)
+    if (q.algo < SS_SMOOTHED || q.algo > SS_HIGHSPACE)
         return fail_msg(SS_EINVAL, "unknown algo");
     if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH))
         return fail_msg(SS_EINVAL, "unknown flags");
@@ -515,6 +515,9 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
     if (R.algo == SS_LOWSPACE)
         return lowspace_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split,
                                   stats);
+    if (R.algo == SS_MEDIUMSPACE || R.algo == SS_HIGHSPACE)
+        return prefix_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split, stats,
+                                R.algo == SS_HIGHSPACE);
     if ((rc = check_lines(n, R)))
         return rc;
     if (R.algo == SS_HYBRID) {
@@ -602,6 +605,8 @@ size_t ss_aux_bytes(size_t n, int dtype, int algo)
                       sizeof(uint64_t);
     if (algo == SS_LOWSPACE || algo == SS_HYBRID)  // hybrid: Low-Space arrays for the middle region (< n)
         return ws + lowspace_aux_bytes(n);
+    if (algo == SS_MEDIUMSPACE || algo == SS_HIGHSPACE)
+        return ws + prefix_aux_bytes(n, dtype, algo == SS_HIGHSPACE);
     return ws;
 }
 

@@ -139,5 +139,8 @@ uint64_t quicksort_leaf_cap(int dtype);
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats);
 size_t lowspace_aux_bytes(size_t n);
+int prefix_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                     uint64_t *d_split, size_t *h_split, ss_stats *stats, bool explicit_prefix);
+size_t prefix_aux_bytes(size_t n, int dtype, bool explicit_prefix);
 
 }  // namespace ss

@@ -337,6 +337,77 @@ __global__ void __launch_bounds__(kNT) k_reorder_tail(Args a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The Medium- and High-Space comparators (Section 5.1): the standard parallel
+// partition with an n-sized output array.  The predecessor counts of blocks
+// of 64 elements and their prefix sums are formed as above (with the roles
+// never swapped); every element is then written to its place in the output
+// array -- predecessors to rank, successors to split + (index - rank), a
+// stable partition -- and the output is copied back.  Medium-Space keeps only
+// the block prefixes (n/64 words); High-Space first writes every element's
+// prefix into an explicit n-word array, as the standard algorithm does.
+
+__global__ void k_ps_init(Args a)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 2)
+        a.ctl[threadIdx.x] = 0;  // count unknown, roles not swapped
+}
+
+// Predecessors before this lane's element of block b (m: the block's ballot).
+__device__ __forceinline__ uint64_t ps_before(const Args &a, uint64_t b, uint64_t m)
+{
+    return a.wgsum[b / kBlocksPerWg] + a.blk[b] + lanes_below(m);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ps_scatter(Args a, T *out)
+{
+    const T *A = reinterpret_cast<const T *>(a.base);
+    const int lane = threadIdx.x & 63;
+    const uint64_t nblk = (a.n + kBlock - 1) / kBlock, split = a.ctl[3];
+    const uint64_t waves = (uint64_t)gridDim.x * (kNT / 64);
+    for (uint64_t b = (uint64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6); b < nblk; b += waves) {
+        const uint64_t x = b * kBlock + lane;
+        bool p = false;
+        T v;
+        if (x < a.n) {
+            v = A[x];
+            p = is_pred(v, a.pivot);
+        }
+        const uint64_t before = ps_before(a, b, __ballot(p));
+        if (x < a.n)
+            out[p ? before : split + x - before] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ps_elem_prefix(Args a, uint64_t *B)
+{
+    const T *A = reinterpret_cast<const T *>(a.base);
+    const int lane = threadIdx.x & 63;
+    const uint64_t nblk = (a.n + kBlock - 1) / kBlock;
+    const uint64_t waves = (uint64_t)gridDim.x * (kNT / 64);
+    for (uint64_t b = (uint64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6); b < nblk; b += waves) {
+        const uint64_t x = b * kBlock + lane;
+        const bool p = x < a.n && is_pred(A[x], a.pivot);
+        const uint64_t before = ps_before(a, b, __ballot(p));
+        if (x < a.n)
+            B[x] = before;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ps_scatter_explicit(Args a, const uint64_t *B, T *out)
+{
+    const T *A = reinterpret_cast<const T *>(a.base);
+    const uint64_t split = a.ctl[3];
+    for (uint64_t x = (uint64_t)blockIdx.x * kNT + threadIdx.x; x < a.n; x += (uint64_t)gridDim.x * kNT) {
+        const T v = A[x];
+        const uint64_t before = B[x];
+        out[is_pred(v, a.pivot) ? before : split + x - before] = v;
+    }
+}
+
 }  // namespace ls
 
 namespace {
@@ -442,6 +513,36 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     return SS_OK;
 }
 
+// The block-count arrays of a call on n elements, cached per (device, stream).
+static int ls_work(int dev, hipStream_t st, size_t n, LsWork **out)
+{
+    hipError_t e;
+    std::lock_guard<std::mutex> lk(g_ls_mu);
+    LsWork *w = &g_ls[std::make_pair(dev, (void *)st)];
+    if (w->cap_n < n) {
+        if (w->ctl)
+            (void)hipFree(w->ctl);
+        *w = LsWork();
+        const size_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
+        const size_t nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
+        const size_t bytes = 8 * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + nwg * sizeof(uint64_t) +
+                             nblk * sizeof(uint32_t) + 256;
+        char *p = nullptr;
+        if ((e = hipMalloc((void **)&p, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_msg(SS_ENOMEM, std::string("Low-Space aux hipMalloc: ") + hipGetErrorString(e));
+        }
+        w->ctl = reinterpret_cast<uint64_t *>(p);
+        w->wg_part = w->ctl + 8;
+        w->wgsum = w->wg_part + kPartMax;
+        w->blk = reinterpret_cast<uint32_t *>(w->wgsum + nwg);
+        w->cap_n = n;
+        w->bytes = bytes;
+    }
+    *out = w;
+    return SS_OK;
+}
+
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats)
 {
@@ -460,31 +561,9 @@ int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Re
     rc = get_workspace(dev, st, &ws);
     if (rc)
         return rc;
-    LsWork *w;
-    {
-        std::lock_guard<std::mutex> lk(g_ls_mu);
-        w = &g_ls[std::make_pair(dev, (void *)st)];
-        if (w->cap_n < n) {
-            if (w->ctl)
-                (void)hipFree(w->ctl);
-            *w = LsWork();
-            const size_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
-            const size_t nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
-            const size_t bytes = 8 * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + nwg * sizeof(uint64_t) +
-                                 nblk * sizeof(uint32_t) + 256;
-            char *p = nullptr;
-            if ((e = hipMalloc((void **)&p, bytes)) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail_msg(SS_ENOMEM, std::string("Low-Space aux hipMalloc: ") + hipGetErrorString(e));
-            }
-            w->ctl = reinterpret_cast<uint64_t *>(p);
-            w->wg_part = w->ctl + 8;
-            w->wgsum = w->wg_part + kPartMax;
-            w->blk = reinterpret_cast<uint32_t *>(w->wgsum + nwg);
-            w->cap_n = n;
-            w->bytes = bytes;
-        }
-    }
+    LsWork *w = nullptr;
+    if ((rc = ls_work(dev, st, n, &w)))
+        return rc;
     RunOut ro;
     std::memset(&ro, 0, sizeof(ro));
     if (n == 0) {
@@ -527,6 +606,151 @@ int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Re
         // and whether the roles were swapped (the array read reversed).
         stats->vmin = pred_count;
         stats->vmax = reversed;
+        stats->bytes_moved = 0;
+    }
+    return SS_OK;
+}
+
+}  // namespace ss
+
+namespace ss {
+
+namespace {
+
+// The n-sized output array (and, for High-Space, the n-word prefix array) of
+// the explicit-space comparators, cached per (device, stream).
+struct PsWork {
+    char *buf = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ps_mu;
+std::map<std::pair<int, void *>, PsWork> g_ps;
+
+template <typename T>
+int prefix_run(char *base, size_t n, uint64_t pivot, hipStream_t st, uint64_t *d_split, Workspace *ws, LsWork &w,
+               char *outbuf, uint64_t *prefix, int cus, uint32_t *launches)
+{
+    ls::Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.base = base;
+    a.n = n;
+    a.pivot = pivot;
+    a.ctl = w.ctl;
+    a.blk = w.blk;
+    a.wgsum = w.wgsum;
+    const uint64_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
+    a.nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
+    a.d_split = d_split;
+    a.host = ws->host_dev;
+    const uint64_t waves_grid = std::min<uint64_t>((nblk + 3) / 4, (uint64_t)cus * 8);
+    T *out = reinterpret_cast<T *>(outbuf);
+    hipLaunchKernelGGL(ls::k_ps_init, dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(ls::k_block_counts<T>, dim3((uint32_t)a.nwg), dim3(ls::kNT), 0, st, a);
+    hipLaunchKernelGGL(ls::k_scan_wg, dim3(1), dim3(1024), 0, st, a);
+    if (prefix) {
+        hipLaunchKernelGGL(ls::k_ps_elem_prefix<T>, dim3((uint32_t)waves_grid), dim3(ls::kNT), 0, st, a, prefix);
+        hipLaunchKernelGGL(ls::k_ps_scatter_explicit<T>, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, (uint64_t)cus * 8)),
+                           dim3(ls::kNT), 0, st, a, (const uint64_t *)prefix, out);
+        *launches += 5;
+    } else {
+        hipLaunchKernelGGL(ls::k_ps_scatter<T>, dim3((uint32_t)waves_grid), dim3(ls::kNT), 0, st, a, out);
+        *launches += 4;
+    }
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess)
+        return fail_device(e, "explicit-space kernel launch");
+    if ((e = hipMemcpyAsync(base, outbuf, n * sizeof(T), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return fail_device(e, "hipMemcpyAsync");
+    return SS_OK;
+}
+
+}  // namespace
+
+size_t prefix_aux_bytes(size_t n, int dtype, bool explicit_prefix)
+{
+    return lowspace_aux_bytes(n) + n * (size_t)elem_size(dtype) + (explicit_prefix ? n * sizeof(uint64_t) : 0);
+}
+
+// Medium-Space (explicit_prefix false) or High-Space (true) partition.
+int prefix_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
+                     uint64_t *d_split, size_t *h_split, ss_stats *stats, bool explicit_prefix)
+{
+    if (d_split && ((uintptr_t)d_split % 8))
+        return fail_msg(SS_EINVAL, "d_split not 8-byte aligned");
+    const bool sync = h_split || stats || (R.flags & SS_FLAG_TIME);
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return fail_device(e, "hipGetDevice");
+    int cus = 0, lds = 0;
+    int rc = device_info(dev, &cus, &lds);
+    if (rc)
+        return rc;
+    Workspace *ws = nullptr;
+    if ((rc = get_workspace(dev, st, &ws)))
+        return rc;
+    LsWork *w = nullptr;
+    if ((rc = ls_work(dev, st, n, &w)))
+        return rc;
+    const size_t need = n * (size_t)elem_size(dtype) + (explicit_prefix ? n * sizeof(uint64_t) : 0) + 256;
+    char *buf = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ps_mu);
+        PsWork &pw = g_ps[std::make_pair(dev, (void *)st)];
+        if (pw.bytes < need) {
+            if (pw.buf)
+                (void)hipFree(pw.buf);
+            pw = PsWork();
+            if ((e = hipMalloc((void **)&pw.buf, need)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail_msg(SS_ENOMEM, std::string("explicit-space output hipMalloc: ") + hipGetErrorString(e));
+            }
+            pw.bytes = need;
+        }
+        buf = pw.buf;
+    }
+    uint64_t *prefix = explicit_prefix
+                           ? reinterpret_cast<uint64_t *>(buf + (n * (size_t)elem_size(dtype) + 255) / 256 * 256)
+                           : nullptr;
+    RunOut ro;
+    std::memset(&ro, 0, sizeof(ro));
+    if (n == 0) {
+        const uint64_t zero = 0;
+        if (d_split && (e = hipMemcpy(d_split, &zero, 8, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail_device(e, "hipMemcpy");
+    } else {
+        if ((R.flags & SS_FLAG_TIME) && (e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
+            return fail_device(e, "hipEventRecord");
+        switch (dtype) {
+        case SS_U32: rc = prefix_run<uint32_t>(base, n, pivot, st, d_split, ws, *w, buf, prefix, cus, &ro.launches); break;
+        case SS_U64: rc = prefix_run<uint64_t>(base, n, pivot, st, d_split, ws, *w, buf, prefix, cus, &ro.launches); break;
+        default: rc = prefix_run<KV>(base, n, pivot, st, d_split, ws, *w, buf, prefix, cus, &ro.launches); break;
+        }
+        if (rc)
+            return rc;
+        if ((R.flags & SS_FLAG_TIME) && (e = hipEventRecord(ws->ev[1], st)) != hipSuccess)
+            return fail_device(e, "hipEventRecord");
+    }
+    if (!sync)
+        return SS_OK;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return fail_device(e, "hipStreamSynchronize");
+    const volatile uint64_t *hres = ws->host;
+    ro.split = n ? hres[1] : 0;
+    ro.done = true;
+    ro.aux_bytes = ws->bytes + prefix_aux_bytes(n, dtype, explicit_prefix);
+    if (R.flags & SS_FLAG_TIME && n) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ws->ev[0], ws->ev[1]);
+        ro.first_level_ms = ms;
+        ro.total_ms = ms;
+    }
+    if (h_split)
+        *h_split = (size_t)ro.split;
+    if (stats) {
+        fill_stats(stats, ro, R, dtype);
+        stats->vmin = ro.split;
+        stats->vmax = ro.split;
         stats->bytes_moved = 0;
     }
     return SS_OK;

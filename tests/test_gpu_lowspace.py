@@ -127,3 +127,37 @@ def test_hybrid_large_and_async(ss):
     assert split == oracle.count_less(a0, p)
     assert oracle.is_partitioned(out, p, split)
     assert oracle.fingerprint(out) == oracle.fingerprint(a0)
+
+
+@pytest.mark.parametrize("algo", ["mediumspace", "highspace"])
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_explicit_space_comparators_parity(ss, algo, kind):
+    """Medium- and High-Space: the standard parallel partition into an n-sized output array."""
+    for n in (1, 2, 63, 64, 65, 4097, 100003, (1 << 20) + 7):
+        a0 = gen(kind, n, 900 + n)
+        keys = a0[:, 0] if a0.ndim == 2 else a0
+        pivots = {0, int(keys.max()) + 1}
+        for q in (0.1, 0.5, 0.9):
+            pivots.add(workloads.pivot_at_quantile_np(a0, q))
+        for p in sorted(pivots):
+            check_against_oracle(ss, a0, p, algo=algo)
+
+
+def test_explicit_space_async_and_aux(ss):
+    import torch
+    n = (1 << 22) + 5
+    a0 = workloads.keys_u64(n, 31)
+    p = workloads.pivot_at_quantile_np(a0, 0.3)
+    for algo in ("mediumspace", "highspace"):
+        t = to_device(a0)
+        d = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+        ss.partition_async(t, p, d, algo=algo)
+        torch.cuda.synchronize()
+        out = to_host(t, a0)
+        split = int(d.item())
+        assert split == oracle.count_less(a0, p)
+        assert oracle.is_partitioned(out, p, split)
+        assert oracle.fingerprint(out) == oracle.fingerprint(a0)
+    med = ss.aux_bytes(n, ss.SS_U64, "mediumspace")
+    high = ss.aux_bytes(n, ss.SS_U64, "highspace")
+    assert med >= n * 8 and high - med == n * 8
