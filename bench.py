@@ -39,9 +39,12 @@ WORKLOADS = {
     # default geometry (512-byte lines, 256 lines per group), pivot 2^63
     "partition_u64_2p30_stride_adv": ("u64", 30, "adv"),
 }
-LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_levelctx.h",
+LEVEL_SOURCES = ["paper_2004_12532_amd/csrc/ss_level_rs.hip", "paper_2004_12532_amd/csrc/ss_level_rs.h",
+                 "paper_2004_12532_amd/csrc/ss_level_xch.hip", "paper_2004_12532_amd/csrc/ss_levelctx.h",
                  "paper_2004_12532_amd/csrc/ss_device.h", "paper_2004_12532_amd/csrc/ss_common.h"]
-COUNTER_FILE = os.path.join(ROOT, "profiles", "level0_u64_2p30_counters.json")
+# Counter summaries of the first level per workload (taken with rocprofv3 --pmc).
+COUNTER_FILES = {"partition_u64_2p30_q0.5": os.path.join(ROOT, "profiles", "level0_u64_2p30_counters.json"),
+                 "partition_u64_2p30_q0.01": os.path.join(ROOT, "profiles", "level0_u64_2p30_q0.01_counters.json")}
 
 
 def level_source_digest() -> str:
@@ -52,13 +55,13 @@ def level_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(n_bytes_alg: float):
+def counter_traffic(workload: str):
     """HBM bytes per launch of the first-level kernel from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary of this workload, if it was taken on the current kernel source; else None."""
     try:
-        with open(COUNTER_FILE) as f:
+        with open(COUNTER_FILES[workload]) as f:
             c = json.load(f)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if c.get("kernel_source_digest") != level_source_digest():
         return None
@@ -120,6 +123,9 @@ def run_partition(args, workload, algo="smoothed"):
     import paper_2004_12532_amd as ss
     import workloads
 
+    algo, _, mode = algo.partition("+")
+    modes = {"auto": "auto", "off": False, "all": True, "skewed": "skewed"}
+    exchange = modes[mode] if mode else modes[args.exchange]
     dtype, log2n, q = WORKLOADS[workload]
     n = 1 << log2n
     w = 8
@@ -137,7 +143,7 @@ def run_partition(args, workload, algo="smoothed"):
     expected = int((workloads.to_unsigned_order(pristine) <
                     workloads.to_unsigned_order(_u64_tensor_scalar(torch, pivot, dev))).sum().item())
     bufs = [torch.empty_like(pristine) for _ in range(args.steps)]
-    kw = dict(algo=algo, b=args.b, tile_bytes=args.tile_bytes)
+    kw = dict(algo=algo, b=args.b, tile_bytes=args.tile_bytes, exchange=exchange)
 
     def restore(k):
         bufs[k].copy_(pristine)
@@ -165,7 +171,14 @@ def run_partition(args, workload, algo="smoothed"):
     alg_bytes = 2.0 * n * w
     value = alg_bytes * args.steps / wall / 1e9
     mean_level_ms = sum(level_ms) / len(level_ms)
-    achieved = alg_bytes / (mean_level_ms / 1e3) / 1e9
+    # The first level's algorithmic bytes: 2 n w in the stable form; in the
+    # exchange form it reads n w and writes only the elements it stored.
+    first_bytes = alg_bytes
+    if stats["exchange_levels"]:
+        sizes = [hi - lo for lo, hi in zip(stats["level_lo"], stats["level_hi"])]
+        rest = sum((1 if l < stats["exchange_levels"] else 2) * w * sz for l, sz in enumerate(sizes) if l >= 1)
+        first_bytes = float(stats["bytes_moved"] - rest)
+    achieved = first_bytes / (mean_level_ms / 1e3) / 1e9
 
     probe = None
     if not args.no_probe:
@@ -175,8 +188,8 @@ def run_partition(args, workload, algo="smoothed"):
     del bufs
     torch.cuda.empty_cache()
 
-    traffic = counter_traffic(alg_bytes) if (algo == "smoothed" and workload == "partition_u64_2p30_q0.5"
-                                              and not args.b and not args.tile_bytes) else None
+    traffic = counter_traffic(workload) if (algo == "smoothed" and exchange == "auto"
+                                            and not args.b and not args.tile_bytes) else None
     out = {
         "metric": "partition GB/s & % HBM peak, 2^30 u64; batched vs per-array launch; p99 latency",
         "value": round(value, 2),
@@ -195,6 +208,7 @@ def run_partition(args, workload, algo="smoothed"):
             "n": n,
             "pivot_quantile": q,
             "algo": algo,
+            "exchange": exchange,
             "b": stats["b"],
             "s_max": stats["s_max"],
             "grid": stats["grid"],
@@ -215,14 +229,21 @@ def run_partition(args, workload, algo="smoothed"):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel": {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
+            "kernel": ({"smoothed": "k_level_rs<uint64_t,256,8,first,exchange> (first Partial Partition Step, "
+                                    "write-minimal exchange form chosen from the key sample)",
+                        "strided": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step, offsets 0, "
+                                   "exchange form)",
+                        "hybrid": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step before the "
+                                  "Low-Space pass over the middle, exchange form)"}.get(algo)
+                       if stats["exchange_levels"] else None) or
+                      {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
                        "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
                        "lowspace": "whole Low-Space call (all its kernels)",
                        "hybrid": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step before the "
                                  "Low-Space pass over the middle)",
                        "mediumspace": "whole Medium-Space call (all its kernels and the copy back)",
                        "highspace": "whole High-Space call (all its kernels and the copy back)"}[algo],
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_launch": first_bytes,
         },
         "probe": probe,
     }
@@ -420,6 +441,10 @@ def main():
                     choices=["smoothed", "strided", "lowspace", "hybrid", "mediumspace", "highspace"])
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--tile-bytes", type=int, default=0)
+    ap.add_argument("--exchange", choices=["auto", "off", "all", "skewed"], default="auto",
+                    help="single-array partitions: the library's choice from a key sample (auto), the stable "
+                         "partition of every group (off), the write-minimal exchange of misplaced pairs in every "
+                         "group (all) or only in groups with few of them (skewed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=120)

@@ -104,6 +104,27 @@ enum ss_status {
 #define SS_FLAG_XCD_ORDER 8u   /* register engines: consecutive groups on the same XCD */
 #define SS_FLAG_GRAPH 16u      /* batched calls: issue the level chain as a captured HIP graph, cached per
                                   (stream, buffers, batch shape) and replayed when they recur */
+#define SS_FLAG_EXCHANGE 32u   /* single-array Smoothed Striding, Strided and Hybrid calls: partition
+                                  each group by the two-pointer exchange of Section 4 (the k-th
+                                  successor from the front below c_i swaps with the k-th predecessor
+                                  from the back above it) and write only the swapped elements.  Same
+                                  split and sides; each group ends as a serial two-pointer partition
+                                  of its slot sequence leaves it.  At a skewed pivot most lines are
+                                  only read.  Register engines; with SS_ENGINE_AUTO it selects one. */
+#define SS_FLAG_EXCHANGE_SKEWED 64u /* as SS_FLAG_EXCHANGE, but only for groups whose misplaced pairs
+                                  are at most 1/32 of their slots; the other groups take the stable
+                                  partition.  Same split and sides; the arrangement depends on which
+                                  groups were skewed. */
+#define SS_FLAG_STABLE 128u    /* never use the exchange form (see below) */
+/* Without SS_FLAG_EXCHANGE, SS_FLAG_EXCHANGE_SKEWED or SS_FLAG_STABLE, a
+ * Smoothed Striding, Strided or Hybrid call on at least 2^22 elements of 8 or
+ * 16 bytes with default engine, b and tile_bytes chooses the form of its first
+ * level from a sample of 4096 keys at fixed positions (64 runs of 64 keys
+ * spread evenly over the array): the exchange form
+ * with 32768-byte groups when at most 1/16 (8-byte keys) or 1/10 (16-byte
+ * records) of them, or at least 15/16 or 9/10, are predecessors, else the
+ * stable form.  The choice depends only on the input,
+ * so a call stays deterministic; ss_stats.exchange_levels reports it. */
 
 /* Tuning parameters; a zero field means "choose automatically". */
 typedef struct ss_params {
@@ -161,7 +182,11 @@ typedef struct ss_stats {
     uint64_t vmin, vmax;                 /* splitting-position range after the last level run */
     float first_level_ms;                /* SS_FLAG_TIME: duration of the first level kernel */
     float total_ms;                      /* SS_FLAG_TIME: duration of the whole call on the stream */
-    uint64_t bytes_moved;                /* algorithmic HBM bytes: 2 * elem_size * sum of level sizes */
+    uint64_t bytes_moved;                /* algorithmic HBM bytes: 2 * elem_size * sum of level sizes; a
+                                            level in the exchange form counts its reads and the elements
+                                            it stored */
+    uint32_t exchange_levels;            /* leading levels run in the write-minimal exchange form */
+    uint32_t reserved;
 } ss_stats;
 
 /* Partition d_ptr[0, n) in place by key < pivot with Recursive Smoothed

@@ -30,7 +30,8 @@ SS_U32, SS_U64, SS_KV16 = 1, 2, 3
 SMOOTHED, STRIDED, LOWSPACE, HYBRID, MEDIUMSPACE, HIGHSPACE = 0, 1, 2, 3, 4, 5
 ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE, "hybrid": HYBRID,
          "mediumspace": MEDIUMSPACE, "highspace": HIGHSPACE}
-FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH = 1, 2, 4, 8, 16
+FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH, FLAG_EXCHANGE, FLAG_EXCHANGE_SKEWED, FLAG_STABLE = \
+    1, 2, 4, 8, 16, 32, 64, 128
 MAX_LEVELS = 32
 STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",
           -5: "SS_EINCOMPLETE"}
@@ -76,7 +77,7 @@ class Stats(ctypes.Structure):
                 ("level_g", ctypes.c_uint32 * MAX_LEVELS), ("level_s", ctypes.c_uint32 * MAX_LEVELS),
                 ("vmin", ctypes.c_uint64), ("vmax", ctypes.c_uint64),
                 ("first_level_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
-                ("bytes_moved", ctypes.c_uint64)]
+                ("bytes_moved", ctypes.c_uint64), ("exchange_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         nl = self.levels
@@ -86,7 +87,7 @@ class Stats(ctypes.Structure):
             "level_lo": list(self.level_lo[:nl]), "level_hi": list(self.level_hi[:nl]),
             "level_g": list(self.level_g[:nl]), "level_s": list(self.level_s[:nl]),
             "vmin": self.vmin, "vmax": self.vmax, "first_level_ms": self.first_level_ms,
-            "total_ms": self.total_ms, "bytes_moved": self.bytes_moved,
+            "total_ms": self.total_ms, "bytes_moved": self.bytes_moved, "exchange_levels": self.exchange_levels,
         }
 
 
@@ -178,10 +179,15 @@ ENGINES = {"auto": 0, "lds": 1, "regs": 2, "regs2": 3}
 
 
 def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False,
-                engine="auto", stream=False, xcd_order=False, graph=False) -> Params:
+                engine="auto", stream=False, xcd_order=False, graph=False, exchange="auto") -> Params:
+    """exchange: "auto" (the library chooses the first level's form from a
+    sample), False (stable partition of every group), True (write-minimal
+    exchange of every group) or "skewed" (exchange only the groups with few
+    misplaced pairs)."""
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0) | (FLAG_STREAM if stream else 0) \
-        | (FLAG_XCD_ORDER if xcd_order else 0) | (FLAG_GRAPH if graph else 0)
+        | (FLAG_XCD_ORDER if xcd_order else 0) | (FLAG_GRAPH if graph else 0) \
+        | {"auto": 0, "skewed": FLAG_EXCHANGE_SKEWED, True: FLAG_EXCHANGE, False: FLAG_STABLE}[exchange]
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
     return Params(a, b, tile_bytes, max_levels, seed, flags, e)
 

@@ -19,8 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ss_level.hip", "ss_level_rs.hip", "ss_strided.hip", "ss_lowspace.hip", "ss_quicksort.hip", "ss_batched.hip",
-           "ss_serving.hip", "ss_probe.hip", "ss_api.cpp"]
+SOURCES = ["ss_level.hip", "ss_level_rs.hip", "ss_level_xch.hip", "ss_strided.hip", "ss_lowspace.hip",
+           "ss_quicksort.hip", "ss_batched.hip", "ss_serving.hip", "ss_probe.hip", "ss_api.cpp"]
 
 FLAGS = [
     "--offload-arch=" + ARCH,

@@ -42,7 +42,7 @@ struct DevInfo {
     int cus = 0;
     int lds = 0;
     int major = 0, minor = 0;
-    std::map<const void *, int> occupancy;
+    std::map<std::pair<const void *, size_t>, int> occupancy;
 };
 std::map<int, DevInfo> g_dev;
 std::map<std::pair<int, void *>, Workspace> g_ws;
@@ -70,22 +70,23 @@ int device_info(int dev, int *cus, int *lds)
     return SS_OK;
 }
 
-int occupancy(int dev, const void *fn, int nt, int *blocks)
+int occupancy(int dev, const void *fn, int nt, int *blocks, size_t shmem)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     DevInfo &d = g_dev[dev];
-    auto it = d.occupancy.find(fn);
+    const auto key = std::make_pair(fn, shmem);
+    auto it = d.occupancy.find(key);
     if (it != d.occupancy.end()) {
         *blocks = it->second;
         return SS_OK;
     }
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, shmem);
     if (e != hipSuccess)
         return fail_device(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (nb < 1)
         nb = 1;
-    d.occupancy[fn] = nb;
+    d.occupancy[key] = nb;
     *blocks = nb;
     return SS_OK;
 }
@@ -161,13 +162,15 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
         q = *p;
     if (q.algo < SS_SMOOTHED || q.algo > SS_HIGHSPACE)
         return fail_msg(SS_EINVAL, "unknown algo");
-    if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH))
+    if (q.flags &
+        ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH | kExchangeFlags |
+          SS_FLAG_STABLE))
         return fail_msg(SS_EINVAL, "unknown flags");
     if (q.engine > SS_ENGINE_REGS2)
         return fail_msg(SS_EINVAL, "unknown engine");
     uint32_t engine = q.engine ? q.engine : auto_engine;
     if (!q.engine && engine == SS_ENGINE_LDS &&
-        (q.tile_bytes == 131072u || (q.flags & (SS_FLAG_STREAM | SS_FLAG_XCD_ORDER))))
+        (q.tile_bytes == 131072u || (q.flags & (SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | kExchangeFlags))))
         engine = SS_ENGINE_REGS;  // options only the register engine has
     const uint32_t tile = q.tile_bytes ? q.tile_bytes
                          : engine == SS_ENGINE_LDS  ? 32768u
@@ -177,6 +180,8 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
         return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (single-buffer register engine) 131072");
     if ((q.flags & SS_FLAG_STREAM) && engine == SS_ENGINE_LDS)
         return fail_msg(SS_EINVAL, "streaming hints apply to the register engines");
+    if ((q.flags & kExchangeFlags) && engine == SS_ENGINE_LDS)
+        return fail_msg(SS_EINVAL, "the write-minimal exchange applies to the register engines");
     const uint32_t b = q.b ? q.b : kDefaultLineBytes / w;
     const uint64_t line = (uint64_t)b * w;
     if (b == 0 || (b & (b - 1)) || line < 64 || line > 4096 || line > tile)
@@ -194,12 +199,19 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     r->levels = levels;
     r->seed = q.seed ? q.seed : 0x5EEDC0DE2004ull;
     r->flags = q.flags;
+    // The automatic first-level choice needs the default geometry and the
+    // register engine, and pays only for 8- and 16-byte elements.
+    r->auto_xch = !q.engine && !q.tile_bytes && !q.b && w >= 8 && engine == SS_ENGINE_REGS &&
+                  !(q.flags & (kExchangeFlags | SS_FLAG_STABLE | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER)) &&
+                  (q.algo == SS_SMOOTHED || q.algo == SS_STRIDED || q.algo == SS_HYBRID);
     return SS_OK;
 }
 
-#define SS_LDS_VARIANT(D, T, NT, TB) {D, SS_ENGINE_LDS, TB, false, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>}
-#define SS_RS_VARIANT(D, T, E, NT, NV, NTMP, DB) \
-    {D, E, NT * NV * 16, NTMP, NT, &launch_level_rs<T, NT, NV, NTMP, DB>, &level_rs_fn<T, NT, NV, NTMP, DB>}
+#define SS_LDS_VARIANT(D, T, NT, TB) \
+    {D, SS_ENGINE_LDS, TB, false, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr}
+#define SS_RS_VARIANT(D, T, E, NT, NV, NTMP, DB)                                                              \
+    {D, E, NT * NV * 16, NTMP, NT, &launch_level_rs<T, NT, NV, NTMP, DB>, &level_rs_fn<T, NT, NV, NTMP, DB>, \
+     &launch_level_xch<T, NT, NV, NTMP, DB>, &level_xch_fn<T, NT, NV, NTMP, DB>}
 #define SS_RS_ALL(E, NT, NV, NTMP, DB)                                                     \
     SS_RS_VARIANT(SS_U32, uint32_t, E, NT, NV, NTMP, DB), SS_RS_VARIANT(SS_U64, uint64_t, E, NT, NV, NTMP, DB), \
         SS_RS_VARIANT(SS_KV16, KV, E, NT, NV, NTMP, DB)
@@ -267,8 +279,12 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const Variant *V = pick_variant(dtype, R.engine, R.tile, (R.flags & SS_FLAG_STREAM) != 0);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
+    // The exchange table (half a group of 16-bit slot numbers) is dynamic LDS.
+    const bool xch = (R.flags & kExchangeFlags) != 0;
+    if (xch && !V->fn_x)
+        return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
     int occ = 0;
-    rc = occupancy(dev, V->fn(true), V->nt, &occ);
+    rc = occupancy(dev, xch ? V->fn_x(true) : V->fn(true), V->nt, &occ, xch ? (size_t)V->tile / R.w : 0);
     if (rc)
         return rc;
     uint32_t P = (uint32_t)(occ * cus);
@@ -283,7 +299,9 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     if (!Vt)
         return fail_msg(SS_EUNSUPPORTED, "no tail kernel variant");
     int occ_t = 0;
-    rc = occupancy(dev, Vt->fn(false), Vt->nt, &occ_t);
+    if (xch && !Vt->fn_x)
+        return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
+    rc = occupancy(dev, xch ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, &occ_t, xch ? (size_t)Vt->tile / R.w : 0);
     if (rc)
         return rc;
     uint32_t Pt = (uint32_t)(occ_t * cus);
@@ -292,6 +310,28 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const uint32_t log2b_t = (uint32_t)ilog2(128 / R.w), s_max_t = 32768u / 128u;
     ro->aux_bytes = ws->bytes;
     ro->launches = 0;
+    ro->xch_levels = 0;
+    ro->written = 0;
+
+    // Automatic choice for large arrays: the first level is launched as a
+    // pair, the stable form with the default groups and the exchange form
+    // with 32 KiB groups; a one-workgroup sample of the keys sets the gate
+    // word that makes exactly one of them run.
+    const bool autox = R.auto_xch && n >= kAutoExchangeMin;
+    const Variant *Vx = nullptr;
+    uint32_t Px = 0;
+    if (autox) {
+        Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u, false);
+        if (!Vx || !Vx->fn_x)
+            return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
+        int occ_x = 0;
+        rc = occupancy(dev, Vx->fn_x(true), Vx->nt, &occ_x, (size_t)Vx->tile / R.w);
+        if (rc)
+            return rc;
+        Px = (uint32_t)(occ_x * cus);
+        if (Px > (uint32_t)kMaxGrid)
+            Px = kMaxGrid;
+    }
 
     const bool timing = (R.flags & SS_FLAG_TIME) != 0;
     const bool strided = R.algo == SS_STRIDED;
@@ -311,6 +351,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         a.s_max = R.s_max;
         a.strided = strided ? 1u : 0u;
         a.order = (R.flags & SS_FLAG_XCD_ORDER) ? 1u : 0u;
+        a.xch_shift = (R.flags & SS_FLAG_EXCHANGE_SKEWED) ? kSkewShift : 0u;
         uint32_t prev_count = 0;
         const uint64_t *prev = nullptr;
         const uint64_t *prev_ctl = nullptr;
@@ -339,9 +380,39 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                 if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
                     return fail_device(e, "hipEventRecord");
             }
-            if ((e = Vl->launch(first, grid, a, st)) != hipSuccess)
-                return fail_device(e, "level kernel launch");
-            ro->launches++;
+            if (level == 0 && (xch || autox)) {
+                if ((e = launch_xch_prepare(dtype, base, n, pivot, ws->result, xch, st)) != hipSuccess)
+                    return fail_device(e, "exchange prepare launch");
+                ro->launches++;
+            }
+            if (xch)
+                a.written = ws->result + kResultWritten;
+            if (level == 0 && autox) {
+                // the pair: stable form (gate 0), then exchange form (gate 1); the
+                // exchange form leaves the stable form's partial slots alone
+                a.gate = ws->result + kResultGate;
+                a.gate_want = 0;
+                a.gate_keep = 0;
+                if ((e = Vl->launch(first, grid, a, st)) != hipSuccess)
+                    return fail_device(e, "level kernel launch");
+                LevelArgs ax = a;
+                ax.s_max = (uint32_t)(Vx->tile / ((uint64_t)R.b * R.w));
+                const Geo Gx = plan_geo(lo, hi, ax.log2b, ax.s_max);
+                const uint32_t grid_x = Gx.g < Px ? Gx.g : Px;
+                ax.gate_want = 1;
+                ax.gate_keep = grid;
+                ax.written = ws->result + kResultWritten;
+                if ((e = Vx->launch_x(first, grid_x, ax, st)) != hipSuccess)
+                    return fail_device(e, "level kernel launch");
+                ro->launches += 2;
+                a.gate = nullptr;
+                a.written = nullptr;
+                grid = grid_x > grid ? grid_x : grid;
+            } else {
+                if ((e = (xch ? Vl->launch_x : Vl->launch)(first, grid, a, st)) != hipSuccess)
+                    return fail_device(e, "level kernel launch");
+                ro->launches++;
+            }
             if (timing && level == 0) {
                 if ((e = hipEventRecord(ws->ev[1], st)) != hipSuccess)
                     return fail_device(e, "hipEventRecord");
@@ -381,6 +452,14 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         }
         ro->vmin = res[2];
         ro->vmax = res[3];
+        if (xch) {
+            ro->xch_levels = level;
+            ro->written = res[kResultWritten];
+        } else if (autox && res[kResultGate]) {
+            ro->xch_levels = 1;
+            ro->written = res[kResultWritten];
+            ro->grid = Px;
+        }
         if (res[0] || (R.flags & SS_FLAG_ONE_LEVEL)) {
             ro->done = res[0] != 0;
             ro->split = res[1];
@@ -422,12 +501,14 @@ void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype)
             st->level_hi[lv] = ro.level_hi[l];
             st->level_g[lv] = ro.level_g[l];
             st->level_s[lv] = ro.level_s[l];
-            moved += 2ull * elem_size(dtype) * (ro.level_hi[l] - ro.level_lo[l]);
+            // a level in the exchange form reads its region and writes only what it stored
+            moved += (l < ro.xch_levels ? 1ull : 2ull) * elem_size(dtype) * (ro.level_hi[l] - ro.level_lo[l]);
             lv++;
         }
     }
     st->levels = lv;
-    st->bytes_moved = moved;
+    st->bytes_moved = moved + (uint64_t)elem_size(dtype) * ro.written;
+    st->exchange_levels = ro.xch_levels;
 }
 
 }  // namespace ss

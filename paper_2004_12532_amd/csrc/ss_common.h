@@ -85,6 +85,12 @@ struct LevelArgs {
     uint32_t s_max;         // lines-per-group bound
     uint32_t strided;       // 1: every offset is 0 (the Strided Algorithm)
     uint32_t order;         // 1: XCD-grouped assignment of groups to workgroups
+    uint32_t xch_shift;     // exchange form: a group whose misplaced pairs m satisfy m << xch_shift > slots
+                            // is stored stably instead (0: every group by exchange)
+    uint32_t gate_want;     // first level: run only if *gate == gate_want, else only neutral partials
+    uint32_t gate_keep;     //   from workgroup gate_keep on (the other kernel of the pair wrote the rest)
+    const uint64_t *gate;   // null: always run
+    uint64_t *written;      // exchange form: elements stored, summed over the workgroups (null: not kept)
 };
 
 constexpr int kCtlWords = 8;        // words per level record

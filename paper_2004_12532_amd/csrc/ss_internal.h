@@ -19,6 +19,11 @@ constexpr uint32_t kDefaultEngine = SS_ENGINE_REGS;
 constexpr uint32_t kDefaultRegsTile = 131072;
 constexpr uint32_t kDefaultLineBytes = 512;
 constexpr uint32_t kDefaultLevels = 8;
+constexpr uint32_t kExchangeFlags = SS_FLAG_EXCHANGE | SS_FLAG_EXCHANGE_SKEWED;
+constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a group's slots
+constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
+constexpr int kResultWritten = 6;   // result word: elements stored by exchange-form levels
+constexpr int kResultGate = 7;      // result word: 1 when the exchange form was chosen
 
 struct Workspace {
     uint64_t *part = nullptr;    // kMaxLevels x 2 x kMaxGrid partials (device)
@@ -41,6 +46,7 @@ struct Resolved {
     uint32_t levels;
     uint64_t seed;
     uint32_t flags;
+    bool auto_xch;  // choose the first level's form from a sample of the keys
 };
 
 struct RunOut {
@@ -52,6 +58,8 @@ struct RunOut {
     uint32_t launches;
     uint64_t aux_bytes;
     float first_level_ms, total_ms;
+    uint32_t xch_levels;   // leading levels run in the exchange form
+    uint64_t written;      // elements those levels stored
     uint64_t level_lo[SS_MAX_LEVELS], level_hi[SS_MAX_LEVELS];
     uint32_t level_g[SS_MAX_LEVELS], level_s[SS_MAX_LEVELS];
 };
@@ -64,6 +72,9 @@ struct Variant {
     int nt;
     hipError_t (*launch)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
     const void *(*fn)(bool first);
+    // the write-minimal exchange form (register engines; null for the LDS engine)
+    hipError_t (*launch_x)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+    const void *(*fn_x)(bool first);
 };
 
 template <typename T, int NT, int TB>
@@ -74,7 +85,13 @@ template <typename T, int NT, int NV, bool NTMP, bool DB>
 hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int NV, bool NTMP, bool DB>
 const void *level_rs_fn(bool first);
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+template <typename T, int NT, int NV, bool NTMP, bool DB>
+const void *level_xch_fn(bool first);
 const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile, bool stream);
+hipError_t launch_xch_prepare(int dtype, const char *base, uint64_t n, uint64_t pivot, uint64_t *result, bool force,
+                              hipStream_t st);
 hipError_t launch_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl, uint64_t *result,
                          uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host, hipStream_t st);
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
@@ -88,7 +105,7 @@ int check_array(const void *d_ptr, size_t n, int dtype);
 int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_engine = kDefaultEngine);
 int check_lines(uint64_t n, const Resolved &R);
 int device_info(int dev, int *cus, int *lds);
-int occupancy(int dev, const void *fn, int nt, int *blocks);
+int occupancy(int dev, const void *fn, int nt, int *blocks, size_t shmem = 0);
 int get_workspace(int dev, void *stream, Workspace **out);
 void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,

@@ -240,7 +240,8 @@ __global__ void __launch_bounds__(NT) k_level(const LevelArgs a)
 }
 
 // Reduce the last level's partials: result[0] = 1 if the partition is
-// complete, result[1] = split (when complete), result[2..3] = (vmin, vmax).
+// complete, result[1] = split (when complete), result[2..3] = (vmin, vmax);
+// result[4..] belong to earlier kernels of the call and are only copied.
 // d_split (nullable) receives the split or UINT64_MAX.  host (nullable, in
 // mapped host memory) receives the result words and then `nctl` level
 // records starting at `ctl`, so the host reads them without a copy.
@@ -264,6 +265,8 @@ __global__ void __launch_bounds__(256) k_finish(const uint64_t *prev, uint32_t c
         if (threadIdx.x < 4)
             host[threadIdx.x] = threadIdx.x == 0 ? (uint64_t)done : threadIdx.x == 1 ? (done ? lo : ~0ull)
                                                                    : threadIdx.x == 2 ? lo : hi;
+        else if (threadIdx.x < kResultWordsDev)
+            host[threadIdx.x] = result[threadIdx.x];  // words written by earlier kernels of the call
         for (uint32_t k = threadIdx.x; k < nctl * kCtlWords; k += 256)
             host[kResultWordsDev + k] = ctl[k];
     }

@@ -1,0 +1,225 @@
+// ss_level_rs.h -- register-resident Partial Partition Step (kernel template;
+// ss_level_rs.hip instantiates the stable form, ss_level_xch.hip the
+// write-minimal exchange).
+//
+// Same step and same result as the LDS-tile kernel (one Partial Partition
+// Step of Smoothed Striding, Section 4; stable partition of every group
+// U_i's slot sequence, so the arrangement is identical), but the group's
+// elements stay in VGPRs and each element is stored directly to its
+// destination line: predecessors to slot rank, successors to slot
+// c_i + (slot - rank).  Without an LDS tile the number of resident
+// workgroups per CU is bounded only by registers, so more of a group's bytes
+// are in flight per CU, and groups can be larger (a smaller middle region)
+// at the same occupancy.  Stores are 4/8/16-byte scattered writes; a
+// wavefront's predecessors (and successors) go to consecutive slots, so each
+// store instruction covers a few contiguous runs of lines, which the L2
+// merges into whole-line writes.
+//
+// Per group: (1) load the group's lines into registers (16-byte vectors, 8
+// lanes per 128-byte line); (2) evaluate key < pivot and count predecessors
+// per (round, wave) with ballots; (3) one wave scans those counts; (4) each
+// element's rank is recomputed from the ballots and the element is stored;
+// (5) the next group's loads are issued; (6) thread 0 folds v_i into the
+// workgroup's (v_min, v_max).
+//
+// With the write-minimal exchange (SS_FLAG_EXCHANGE) step (4) instead swaps
+// the misplaced pairs of the group through a table of slot numbers in LDS
+// and writes only those elements: at a skewed pivot most lines are never
+// written.
+//
+// A group whose lines are all real and that fills the whole tile (every
+// group of a level except at most the two touching the region's ends, and
+// the last partial round of small regions) takes a branch-free path; the
+// others take a general path that masks virtual elements (front padding up
+// to the line boundary, padding after the region's end).
+#pragma once
+
+#include "ss_common.h"
+#include "ss_device.h"
+#include "ss_internal.h"
+#include "ss_levelctx.h"
+
+namespace ss {
+
+template <typename T, int NT, int NV, bool FIRST, bool NTMP, bool DB, bool XCH>
+__global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
+{
+    using Ctx = LevelCtx<T, NT, NV, NTMP>;
+    constexpr int W = Ctx::W;
+    constexpr int NW = Ctx::NW;
+    constexpr int MAXS = Ctx::NVEC * 16 / 64;  // lines of at least 64 bytes
+    static_assert(Ctx::E <= 256 && NV * Ctx::V <= 64, "tile shape");
+
+    __shared__ uint32_t xoff[MAXS];
+    __shared__ uint32_t cnt[Ctx::E + 2];
+    __shared__ uint64_t red[2 * NW];
+
+    const int tid = threadIdx.x;
+    const uint32_t bid = blockIdx.x;
+
+    // A first level launched as one of a stable/exchange pair: the kernel the
+    // gate word does not select only leaves neutral partials behind.
+    if (FIRST && a.gate && *a.gate != a.gate_want) {
+        if (tid == 0 && bid >= a.gate_keep) {
+            a.out[2 * bid] = ~0ull;
+            a.out[2 * bid + 1] = 0ull;
+        }
+        return;
+    }
+
+    uint64_t lo, hi;
+    if (FIRST) {
+        lo = a.lo;
+        hi = a.hi;
+    } else {
+        prev_region<NT>(a.prev, a.prev_count, a.prev_ctl, red, lo, hi);
+    }
+    if (!(lo < hi)) {
+        if (tid == 0) {
+            a.out[2 * bid] = bid == 0 ? lo : ~0ull;
+            a.out[2 * bid + 1] = bid == 0 ? lo : 0ull;
+            if (bid == 0) {
+                a.ctl[0] = lo; a.ctl[1] = lo; a.ctl[2] = 0; a.ctl[3] = 0;
+            }
+        }
+        return;
+    }
+
+    const Geo G = plan_geo(lo, hi, a.log2b, a.s_max);
+    Ctx x;
+    x.g = G.g;
+    x.s = G.s;
+    x.fp = G.fp;
+    x.real_end = (uint64_t)G.fp + (hi - lo);
+    x.A0 = a.base + lo * W - (uint64_t)G.fp * W;
+    x.log2b = a.log2b;
+    x.vpl_log2 = a.log2b + Ctx::LOG2W - 4;
+    x.nvec = G.s << x.vpl_log2;
+    x.pivot = a.pivot;
+    x.xoff = xoff;
+    x.cnt = cnt;
+    x.tid = tid;
+    x.lane = tid & 63;
+    x.wid = tid >> 6;
+
+    if (bid == 0 && tid == 0) {
+        a.ctl[0] = lo; a.ctl[1] = hi; a.ctl[2] = G.g; a.ctl[3] = G.s;
+    }
+    for (uint32_t j = tid; j < G.s; j += NT)
+        xoff[j] = a.strided ? 0u : chunk_offset(a.seed, a.level, j, G.g);
+    __syncthreads();
+
+    uint64_t vmin = ~0ull, vmax = 0;
+    auto fold = [&](uint32_t c, uint32_t i) {
+        if (tid == 0) {
+            uint64_t vi;
+            if (c >= (G.s << x.log2b)) {
+                vi = hi;
+            } else {
+                const uint64_t vp =
+                    ((uint64_t)x.line_of(c >> x.log2b, i) << x.log2b) + (c & ((1u << x.log2b) - 1));
+                vi = vp >= x.real_end ? hi : lo + (vp - G.fp);
+            }
+            vmin = vi < vmin ? vi : vmin;
+            vmax = vi > vmax ? vi : vmax;
+        }
+    };
+    using Mask = typename Ctx::Mask;
+    auto load_any = [&](v4u (&buf)[NV], uint32_t i, Mask &m) -> bool {
+        const bool f = x.fast(i);
+        if (f)
+            x.template load<true>(buf, i, m);
+        else
+            x.template load<false>(buf, i, m);
+        return f;
+    };
+    extern __shared__ uint16_t xt[];  // Ctx::XCH_SLOTS entries (exchange form)
+    uint64_t written = 0;             // exchange form: elements this workgroup stored
+    auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f, const Mask &m) -> uint32_t {
+        if constexpr (XCH)
+            return f ? x.template exchange<true>(buf, i, m, xt, a.xch_shift, written)
+                     : x.template exchange<false>(buf, i, m, xt, a.xch_shift, written);
+        else
+            return f ? x.template partition<true>(buf, i, m) : x.template partition<false>(buf, i, m);
+    };
+
+    const uint32_t step = gridDim.x;
+    // Workgroups are dispatched round-robin over the 8 XCDs; with order = 1 the
+    // groups a workgroup starts from are renumbered so that consecutive groups
+    // (adjacent lines of every chunk) run on the same XCD.
+    const uint32_t first = (a.order && (step & 7) == 0) ? (bid & 7) * (step >> 3) + (bid >> 3) : bid;
+    if (!DB) {
+        // One register buffer: the next group's loads are issued after this group's stores.
+        v4u buf[NV];
+        Mask m;
+        uint32_t i = first;
+        bool fast = false;
+        if (i < G.g)
+            fast = load_any(buf, i, m);
+        while (i < G.g) {
+            fold(part_any(buf, i, fast, m), i);
+            i += step;
+            if (i < G.g)
+                fast = load_any(buf, i, m);
+            __syncthreads();  // the counts are rewritten by the next group
+        }
+    } else {
+        // Two register buffers: the next group's loads are issued before this group is partitioned.
+        v4u ba[NV], bb[NV];
+        Mask ma, mb;
+        uint32_t i = first;
+        bool fa = false, fb = false;
+        if (i < G.g)
+            fa = load_any(ba, i, ma);
+        while (i < G.g) {
+            if (i + step < G.g)
+                fb = load_any(bb, i + step, mb);
+            fold(part_any(ba, i, fa, ma), i);
+            __syncthreads();
+            i += step;
+            if (i >= G.g)
+                break;
+            if (i + step < G.g)
+                fa = load_any(ba, i + step, ma);
+            fold(part_any(bb, i, fb, mb), i);
+            __syncthreads();
+            i += step;
+        }
+    }
+    if (tid == 0) {
+        a.out[2 * bid] = vmin;
+        a.out[2 * bid + 1] = vmax;
+        if (XCH && a.written && written)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.written), (unsigned long long)written);
+    }
+}
+
+// Launch of the stable form (XCH = false) or the exchange form (XCH = true),
+// whose table of slot numbers is dynamic LDS.
+template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
+hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
+{
+    const size_t shmem = XCH ? LevelCtx<T, NT, NV, NTMP>::XCH_SLOTS * sizeof(uint16_t) : 0;
+    if (first)
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+    else
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
+const void *level_rs_fn_t(bool first)
+{
+    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, NTMP, DB, XCH>)
+                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, NTMP, DB, XCH>);
+}
+
+// Every register-engine variant the host selects from: single buffer with
+// groups of 32, 64 and 128 KiB, double buffer with 32 and 64 KiB, each with
+// and without streaming hints.  X(T, NT, NV, NTMP, DB) is applied to each.
+#define SS_RS_VARIANTS(X, T)                                                                        \
+    X(T, 256, 8, false, false) X(T, 512, 8, false, false) X(T, 512, 16, false, false)               \
+    X(T, 256, 8, true, false) X(T, 512, 8, true, false) X(T, 512, 16, true, false)                  \
+    X(T, 512, 4, false, true) X(T, 512, 8, false, true) X(T, 512, 4, true, true) X(T, 512, 8, true, true)
+
+}  // namespace ss

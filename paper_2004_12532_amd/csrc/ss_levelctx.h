@@ -2,8 +2,9 @@
 // Step (Section 4) with the group held in registers: load the group's lines,
 // rank its predecessors with wavefront ballots and a scan of per-wave counts,
 // and store every element at its slot of the stable partition of the group
-// (predecessors to slot rank, successors to slot c_i + slot - rank).  Shared
-// by the single-array level kernel and the batched kernel.
+// (predecessors to slot rank, successors to slot c_i + slot - rank), or, in
+// the write-minimal form, swap only the misplaced pairs.  Shared by the
+// single-array level kernel and the batched kernel.
 #pragma once
 
 #include "ss_common.h"
@@ -135,9 +136,11 @@ struct LevelCtx {
         return bits;
     }
 
-    // Stable partition of group i; returns its predecessor count c_i.
+    // Count the group's predecessors: per-(round, wave) counts, scanned by
+    // wave 0 into exclusive offsets cnt[0..E) and the total cnt[E] = c_i.
+    // Returns the decider bits of this thread's slots (bit r * V + e).
     template <bool FAST>
-    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i, const Mask &m) const
+    __device__ __forceinline__ uint64_t count(const v4u (&buf)[NV], const Mask &m) const
     {
         uint64_t pb = 0;
 #pragma unroll
@@ -180,8 +183,14 @@ struct LevelCtx {
                 cnt[E] = inc;
         }
         __syncthreads();
-        const uint32_t c = cnt[E];
-        const uint32_t b = 1u << log2b;
+        return pb;
+    }
+
+    // Visit every slot of this thread in order with its rank among the
+    // group's predecessors: f(r, e, slot, is_pred, preds before the slot).
+    template <typename F>
+    __device__ __forceinline__ void for_ranks(uint64_t pb, F &&f) const
+    {
 #pragma unroll
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
@@ -193,15 +202,112 @@ struct LevelCtx {
 #pragma unroll
             for (int e = 0; e < V; e++) {
                 const bool p = (bits >> e) & 1;
-                const uint32_t slot = q * V + e;
-                const uint32_t d = p ? rp : c + slot - rp;
+                f(r, e, q * V + e, p, rp);
                 rp += p;
-                if (FAST || ((m.real >> (r * V + e)) & 1)) {
-                    const uint64_t vd = ((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1));
-                    store_elem<NTMP, T>(buf[r], e, elem_ptr(vd));
-                }
             }
         }
+    }
+
+    __device__ __forceinline__ char *slot_ptr(uint32_t d, uint32_t i) const
+    {
+        const uint32_t b = 1u << log2b;
+        return elem_ptr(((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1)));
+    }
+
+    // Store every real element at its slot of the stable partition.
+    template <bool FAST>
+    __device__ __forceinline__ void store_stable(const v4u (&buf)[NV], uint32_t i, const Mask &m, uint64_t pb,
+                                                 uint32_t c) const
+    {
+        for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
+            if (FAST || ((m.real >> (r * V + e)) & 1))
+                store_elem<NTMP, T>(buf[r], e, slot_ptr(p ? rp : c + slot - rp, i));
+        });
+    }
+
+    // Stable partition of group i; returns its predecessor count c_i.
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t partition(const v4u (&buf)[NV], uint32_t i, const Mask &m) const
+    {
+        const uint64_t pb = count<FAST>(buf, m);
+        const uint32_t c = cnt[E];
+        store_stable<FAST>(buf, i, m, pb, c);
+        return c;
+    }
+
+    // Slots of the exchange table: a group has at most S / 2 misplaced pairs.
+    static constexpr int XCH_SLOTS = NVEC * V / 2;
+
+    // Write-minimal partition of group i (the two-pointer exchange of the
+    // serial step, Section 4): the k-th successor from the front of the slot
+    // order that lies in [0, c_i) swaps with the k-th predecessor from the
+    // back that lies in [c_i, S).  These are exactly the pairs a serial
+    // two-pointer scan of the slot sequence swaps, so the group ends in the
+    // same arrangement, and only the swapped elements are written.  Every
+    // misplaced element is real: virtual front slots are predecessors below
+    // c_i and virtual tail slots successors above it.  xt holds XCH_SLOTS
+    // 16-bit slot numbers of LDS.
+    //
+    // The group first counts its misplaced pairs m_i: c_i minus the
+    // predecessors below slot c_i, read from the rank of slot c_i (one more
+    // word of LDS at cnt[E + 1]).  With shift > 0 it falls back to the stable
+    // partition when m_i << shift exceeds its slot count: once a few percent
+    // of the elements move, the swapped elements dirty nearly every line
+    // anyway and the exchange's extra passes cost more than they save.
+    // shift = 0 exchanges every group.  `written` grows by the elements the
+    // group stores (2 m_i, or its slot count when stored stably).  Returns c_i.
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t exchange(const v4u (&buf)[NV], uint32_t i, const Mask &m,
+                                                 uint16_t *xt, uint32_t shift, uint64_t &written) const
+    {
+        const uint64_t pb = count<FAST>(buf, m);
+        const uint32_t c = cnt[E];
+        const uint32_t S = nvec * V;
+        uint32_t mis = 0;
+        if (c < S) {
+            // slot c_i is element e of vector q = r * NT + t (r uniform over the workgroup)
+            const uint32_t q = c / V, e = c % V, r = q / NT, t = q % NT;
+            if ((uint32_t)wid == t / 64) {
+                const uint32_t bits = (uint32_t)(pb >> (r * V)) & ((1u << V) - 1);
+                uint32_t rp = cnt[r * NW + wid];
+#pragma unroll
+                for (int k = 0; k < V; k++)
+                    rp += lanes_below(__ballot((bits >> k) & 1));
+                if ((uint32_t)lane == t % 64)
+                    cnt[E + 1] = rp + __popc(bits & ((1u << e) - 1));
+            }
+            __syncthreads();
+            mis = c - cnt[E + 1];
+        }
+        if (shift && (mis << shift) > S) {
+            store_stable<FAST>(buf, i, m, pb, c);
+            written += S;
+            return c;
+        }
+        written += 2ull * mis;
+        if (mis == 0)
+            return c;
+        // (1) each misplaced successor posts its slot under its front rank
+        for_ranks(pb, [&](int, int, uint32_t slot, bool p, uint32_t rp) {
+            if (!p && slot < c)
+                xt[slot - rp] = (uint16_t)slot;
+        });
+        __syncthreads();
+        // (2) each misplaced predecessor takes its partner's slot, stores
+        // itself there and posts its own slot in exchange
+        for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
+            if (p && slot >= c) {
+                const uint32_t k = c - rp - 1;
+                store_elem<NTMP, T>(buf[r], e, slot_ptr(xt[k], i));
+                xt[k] = (uint16_t)slot;
+            }
+        });
+        __syncthreads();
+        // (3) each misplaced successor stores itself at its partner's slot
+        for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
+            if (!p && slot < c)
+                store_elem<NTMP, T>(buf[r], e, slot_ptr(xt[slot - rp], i));
+        });
         return c;
     }
 };

@@ -42,6 +42,8 @@ __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, cons
     }
     if (host && tid < kCtlWords)
         host[kResultWordsDev + tid] = ctl[tid];
+    if (host && tid >= 4 && tid < kResultWordsDev)
+        host[tid] = result[tid];
 }
 
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,

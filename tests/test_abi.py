@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import paper_2004_12532_amd as ss
     assert ctypes.sizeof(ss.Params) == 32
-    # split, aux, 6 x u32, 2 x 32 x u64, 2 x 32 x u32, vmin, vmax, 2 floats, bytes_moved
-    assert ctypes.sizeof(ss.Stats) == 8 + 8 + 24 + 2 * 32 * 8 + 2 * 32 * 4 + 16 + 8 + 8
+    # split, aux, 6 x u32, 2 x 32 x u64, 2 x 32 x u32, vmin, vmax, 2 floats, bytes_moved, 2 x u32
+    assert ctypes.sizeof(ss.Stats) == 8 + 8 + 24 + 2 * 32 * 8 + 2 * 32 * 4 + 16 + 8 + 8 + 8
     # nclass, 8 x b, 8 x group_bytes, (pad), 8 x max_len, 8 x ms
     assert ctypes.sizeof(ss.Tuning) == 4 + 32 + 32 + 4 + 64 + 32
 
@@ -53,7 +53,7 @@ def test_argument_validation_without_device():
     assert L.ss_partition(ctypes.c_void_p(0x1000), 10, ss.SS_U64, 5, None) == -1        # no split out
     for bad in (ss.make_params(b=3), ss.make_params(b=4), ss.make_params(b=1024), ss.make_params(tile_bytes=4096),
                 ss.make_params(max_levels=33), ss.make_params(algo=7),
-                ss.make_params(engine="lds", tile_bytes=131072)):
+                ss.make_params(engine="lds", tile_bytes=131072), ss.make_params(engine="lds", exchange=True)):
         rc = L.ss_partition_ex(ctypes.c_void_p(0x1000), 10, ss.SS_U64, 5, ctypes.byref(bad), None, None,
                                ctypes.byref(split), None)
         assert rc == -1, (bad.b, bad.tile_bytes, bad.max_levels, bad.algo)
@@ -97,3 +97,16 @@ def test_server_engine_argument_validation_without_device():
     assert L.ss_server_submit(None, 0, 0, 1, 0, 0) == -1
     assert L.ss_server_tick(None, 1) == -1
     assert ss.server_job_aux_bytes(ss.SS_KV16, 1, 1 << 20) > ss.server_job_aux_bytes(ss.SS_KV16, 0, 1 << 20)
+
+
+def test_struct_sizes_equal_the_c_compilers(tmp_path):
+    """The ctypes mirrors have the sizes a C compiler gives the header's structs."""
+    import subprocess
+    import paper_2004_12532_amd as ss
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "ss.h"\nint main(void) { printf("%zu %zu %zu\\n", '
+                   'sizeof(ss_params), sizeof(ss_stats), sizeof(ss_batched_tuning)); return 0; }\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    sizes = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert sizes == [ctypes.sizeof(ss.Params), ctypes.sizeof(ss.Stats), ctypes.sizeof(ss.Tuning)]

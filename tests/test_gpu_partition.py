@@ -321,3 +321,167 @@ def test_stride_adversary_middle_regions(ss):
         mids[algo] = st["vmax"] - st["vmin"]
     assert mids["strided"] > 0.95 * n, mids
     assert mids["smoothed"] < 0.5 * n, mids
+
+
+XCH_ENGINES = [("regs", 32768), ("regs", 65536), ("regs", 131072), ("regs2", 32768), ("regs2", 65536)]
+
+
+@pytest.mark.parametrize("engine,tile", XCH_ENGINES)
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+@pytest.mark.parametrize("algo", ["smoothed", "strided"])
+def test_exchange_level_equals_serial_step(ss, kind, algo, engine, tile):
+    """Write-minimal exchange: one Partial Partition Step leaves the array byte for
+    byte as the oracle's serial two-pointer step over every group's slot sequence."""
+    for n, seed, q in ((1 << 18, 1, 0.5), (123457, 2, 0.1), (300000, 3, 0.99), (40000, 4, 0.01), (5000, 5, 0.5)):
+        a0 = gen(kind, n, seed)
+        p = workloads.pivot_at_quantile_np(a0, q)
+        t = to_device(a0)
+        split, st = ss.partition(t, p, stats=True, one_level=True, algo=algo, seed=77 + seed, engine=engine,
+                                 tile_bytes=tile, exchange=True)
+        out = to_host(t, a0)
+        g, s, b = st["level_g"][0], st["level_s"][0], st["b"]
+        assert s * g * b >= n > (s - 1) * g * b
+        X = np.zeros(s, np.uint32) if algo == "strided" else oracle.ss_offsets(77 + seed, 0, g, s)
+        ref = a0.copy()
+        vmin, vmax, c, v = oracle.ss_partial_step(ref, b, g, s, X, p)
+        assert (st["vmin"], st["vmax"]) == (vmin, vmax)
+        assert np.array_equal(out, ref), (n, q)
+
+
+@pytest.mark.parametrize("mode", [True, "skewed"])
+@pytest.mark.parametrize("engine,tile", XCH_ENGINES)
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_exchange_parity(ss, kind, engine, tile, mode):
+    """The whole recursion with the exchange form (every group, or only the skewed
+    ones): split and sides equal the oracle's."""
+    for n in (1, 2, 15, 16, 17, 127, 129, 8193, 65537, 300001, 1 << 20):
+        a0 = gen(kind, n, 2000 + n)
+        for q in (0.0, 0.01, 0.03, 0.1, 0.5, 0.97, 1.0):
+            p = workloads.pivot_at_quantile_np(a0, q) if q < 1.0 else U64MAX
+            check_against_oracle(ss, a0, p, engine=engine, tile_bytes=tile, exchange=mode)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_skewed_exchange_level_groups(ss, kind):
+    """Skewed mode, one level: each group is either exchanged or stably partitioned,
+    so (v_min, v_max), the side of every position and every group's multiset equal
+    the oracle's step; an already partitioned input is left byte for byte as it was."""
+    for n, seed, q in ((1 << 18, 1, 0.5), (300000, 3, 0.02), (123457, 2, 0.97)):
+        a0 = gen(kind, n, seed)
+        p = workloads.pivot_at_quantile_np(a0, q)
+        t = to_device(a0)
+        _, st = ss.partition(t, p, stats=True, one_level=True, seed=88 + seed, exchange="skewed")
+        out = to_host(t, a0)
+        g, s, b = st["level_g"][0], st["level_s"][0], st["b"]
+        X = oracle.ss_offsets(88 + seed, 0, g, s)
+        ref = a0.copy()
+        vmin, vmax, _, _ = oracle.ss_partial_step(ref, b, g, s, X, p)
+        assert (st["vmin"], st["vmax"]) == (vmin, vmax)
+        gk = out[:, 0] if out.ndim == 2 else out
+        rk = ref[:, 0] if ref.ndim == 2 else ref
+        assert np.array_equal(gk < p, rk < p)
+        grp = _group_of_position(n, b, g, s, X)
+        assert np.array_equal(gk[np.lexsort((gk, grp))], rk[np.lexsort((rk, grp))])
+        done = ref.copy()
+        oracle.partition(done, p)
+        t = to_device(done)
+        ss.partition(t, p, exchange="skewed")
+        assert np.array_equal(to_host(t, done), done)
+
+
+def test_exchange_structured_and_unaligned(ss):
+    base = workloads.keys_u64(70001, 15)
+    for k in (base % 7, np.zeros_like(base) + 3, np.sort(base), np.sort(base)[::-1].copy()):
+        for q in (0.0, 0.3, 0.5, 0.99):
+            check_against_oracle(ss, k, workloads.pivot_at_quantile_np(k, q), exchange=True)
+    full = gen("u64", 50064, 78)
+    t_full = to_device(full)
+    for off in (0, 1, 3, 7, 13, 31):
+        length = 50000 - off
+        sub = full[off:off + length].copy()
+        p = workloads.pivot_at_quantile_np(sub, 0.05)
+        t = t_full.clone()
+        split = ss.partition(t[off:off + length], p, exchange=True)
+        out = to_host(t, full)
+        assert np.array_equal(out[:off], full[:off]) and np.array_equal(out[off + length:], full[off + length:])
+        ref = sub.copy()
+        assert split == oracle.partition(ref, p)
+        gl, gr = oracle.sorted_sides(out[off:off + length], split)
+        rl, rr = oracle.sorted_sides(ref, split)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+
+
+def test_exchange_hybrid_and_stride_adversary(ss):
+    n = (1 << 20) + 77
+    g = workloads.stride_groups(n, 64, 256)
+    a0 = workloads.stride_adversarial_u64(n, 8, 64, g)
+    for algo in ("smoothed", "strided", "hybrid"):
+        check_against_oracle(ss, a0, 1 << 63, algo=algo, exchange=True)
+    a1 = workloads.keys_u64(1 << 21, 16)
+    check_against_oracle(ss, a1, workloads.pivot_at_quantile_np(a1, 0.02), algo="hybrid", exchange=True)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("q", [0.5, 0.01])
+def test_exchange_full_size_2p30_properties(ss, q):
+    """2^30 uint64 keys with the exchange form: split, sides and multiset."""
+    torch = _torch()
+    n = 1 << 30
+    t = workloads.keys_u64_torch(n, workloads.config_seed(1), "cuda")
+    p = workloads.pivot_at_quantile_torch(t, q)
+    host_in = t.cpu().numpy().view(np.uint64)
+    count = oracle.count_less(host_in, p)
+    fp_in = oracle.fingerprint(host_in)
+    del host_in
+    split = ss.partition(t, p, exchange=True)
+    assert split == count
+    host_out = t.cpu().numpy().view(np.uint64)
+    assert oracle.is_partitioned(host_out, p, split)
+    assert oracle.fingerprint(host_out) == fp_in
+    del t, host_out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", ["u64", "kv"])
+def test_automatic_exchange_choice(ss, kind):
+    """From 2^22 elements on, the default call samples the keys: a skewed pivot
+    selects the exchange form for the first level, a central one the stable form,
+    and both give the oracle's split and sides; the stable flag turns it off."""
+    n = (1 << 22) + 1234
+    a0 = gen(kind, n, 4242)
+    for q, want in ((0.01, 1), (0.98, 1), (0.5, 0), (0.2, 0)):
+        p = workloads.pivot_at_quantile_np(a0, q)
+        t = to_device(a0)
+        split, st = ss.partition(t, p, stats=True)
+        assert st["exchange_levels"] == want, (q, st["exchange_levels"])
+        out = to_host(t, a0)
+        ref = a0.copy()
+        assert split == oracle.partition(ref, p)
+        gl, gr = oracle.sorted_sides(out, split)
+        rl, rr = oracle.sorted_sides(ref, split)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+        w = 16 if kind == "kv" else 8
+        if want:
+            # reads n w, writes fewer than 2 (q (1 - q) + slack) n w in the first level
+            assert st["bytes_moved"] < 2 * n * w
+        t2 = to_device(a0)
+        split2, st2 = ss.partition(t2, p, stats=True, exchange=False)
+        assert split2 == split and st2["exchange_levels"] == 0
+        t3 = to_device(a0)
+        ss.partition(t3, p)
+        assert bool((t3 == t).all())   # the choice depends only on the input
+
+
+def test_automatic_exchange_strided_and_hybrid(ss):
+    a0 = workloads.keys_u64((1 << 22) + 99, 4343)
+    p = workloads.pivot_at_quantile_np(a0, 0.02)
+    for algo in ("strided", "hybrid"):
+        t = to_device(a0)
+        split, st = ss.partition(t, p, stats=True, algo=algo)
+        assert st["exchange_levels"] == 1, algo
+        out = to_host(t, a0)
+        ref = a0.copy()
+        assert split == oracle.partition(ref, p)
+        gl, gr = oracle.sorted_sides(out, split)
+        rl, rr = oracle.sorted_sides(ref, split)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
