@@ -376,14 +376,14 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             a.prev_count = prev_count;
             a.out = ws->part + (size_t)k * 2 * kMaxGrid;
             a.ctl = ws->ctl + (size_t)k * kCtlWords;
-            if (timing && level == 0) {
-                if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
-                    return fail_device(e, "hipEventRecord");
-            }
             if (level == 0 && (xch || autox)) {
                 if ((e = launch_xch_prepare(dtype, base, n, pivot, ws->result, xch, st)) != hipSuccess)
                     return fail_device(e, "exchange prepare launch");
                 ro->launches++;
+            }
+            if (timing && level == 0) {
+                if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
+                    return fail_device(e, "hipEventRecord");
             }
             if (xch)
                 a.written = ws->result + kResultWritten;
