@@ -242,7 +242,8 @@ def run_partition(args, workload, algo="smoothed"):
                        "hybrid": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step before the "
                                  "Low-Space pass over the middle)",
                        "mediumspace": "whole Medium-Space call (all its kernels and the copy back)",
-                       "highspace": "whole High-Space call (all its kernels and the copy back)"}[algo],
+                       "highspace": "whole High-Space call (all its kernels and the copy back)",
+                       "implicit": "whole implicit Blocked-Prefix-Sum call (all its kernels)"}[algo],
             "algorithmic_bytes_per_launch": first_bytes,
         },
         "probe": probe,
@@ -411,6 +412,7 @@ SUITE = ["partition_u64_2p30_q0.1", "partition_u64_2p30_q0.01", "partition_u64_2
          "partition_u64_2p30_stride_adv", "partition_u64_2p30_stride_adv:strided",
          "partition_u64_2p30_q0.5:strided", "partition_u64_2p30_q0.5:lowspace", "partition_u64_2p30_q0.5:hybrid",
          "partition_u64_2p30_q0.5:mediumspace", "partition_u64_2p30_q0.5:highspace",
+         "partition_u64_2p30_q0.5:implicit",
          "quicksort_u32_2p28", "quicksort_u32_2p28_d1024", "batched_u64_20000", "serving_kv16"]
 
 
@@ -438,7 +440,7 @@ def main():
                     choices=sorted(WORKLOADS) + ["quicksort_u32_2p28", "quicksort_u32_2p28_d1024",
                                                  "batched_u64_20000", "serving_kv16"])
     ap.add_argument("--algo", default="smoothed",
-                    choices=["smoothed", "strided", "lowspace", "hybrid", "mediumspace", "highspace"])
+                    choices=["smoothed", "strided", "lowspace", "hybrid", "mediumspace", "highspace", "implicit"])
     ap.add_argument("--b", type=int, default=0)
     ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--exchange", choices=["auto", "off", "all", "skewed"], default="auto",

@@ -78,8 +78,29 @@ enum ss_dtype { SS_U32 = 1, SS_U64 = 2, SS_KV16 = 3 };
  *               predecessor prefix only per block of 64 elements (n/64
  *               words); High-Space also writes every element's prefix into an
  *               n-word array first.  Not in place: ss_aux_bytes reports the
- *               extra n elements (and n words). */
-enum ss_algo { SS_SMOOTHED = 0, SS_STRIDED = 1, SS_LOWSPACE = 2, SS_HYBRID = 3, SS_MEDIUMSPACE = 4, SS_HIGHSPACE = 5 };
+ *               extra n elements (and n words).
+ * SS_IMPLICIT : the Blocked-Prefix-Sum partition of Section 3 as stated, with
+ *               no auxiliary array: the predecessor prefix of every block of
+ *               256 elements is kept in the order of the block's first 64
+ *               element pairs (Lemma bitstore; with repeated elements
+ *               Lemma bitstore2, which may flip the lowest bit of an element
+ *               -- of the payload for SS_KV16 -- while the value is stored
+ *               and restores it before the element is used).  Counting, role
+ *               swap and preprocessing are those of SS_LOWSPACE.  Arrays of at
+ *               most 64 KiB are partitioned by one workgroup directly.
+ *               Auxiliary memory is a constant 33 KiB plus the workspace.
+ *               With SS_FLAG_ONE_LEVEL (arrays above 64 KiB) the call stops
+ *               once every block holds its inclusive prefix: the array is
+ *               then preprocessed and encoded, not partitioned. */
+enum ss_algo {
+    SS_SMOOTHED = 0,
+    SS_STRIDED = 1,
+    SS_LOWSPACE = 2,
+    SS_HYBRID = 3,
+    SS_MEDIUMSPACE = 4,
+    SS_HIGHSPACE = 5,
+    SS_IMPLICIT = 6
+};
 
 enum ss_status {
     SS_OK = 0,

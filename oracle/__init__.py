@@ -146,6 +146,39 @@ def ss_partial_step(a: np.ndarray, b: int, g: int, s: int, X: np.ndarray, pivot:
     return int(vmin[0]), int(vmax[0]), c, v
 
 
+def make_successor_heavy(a: np.ndarray, pivot: int) -> bool:
+    """Preprocessing phase of the Blocked-Prefix-Sum partition (Section 3,
+    MakeSuccessorHeavy; Lemma preprocessingphase), in place.  The roles are
+    swapped first when predecessors (key < pivot) are the majority
+    (ParallelPartition): the logical array L is then `a` read backwards with
+    the decider negated.  For m = n, ceil(n/2), ceil(n/4), ... while m >= 2,
+    and every i < floor(m/2) in parallel: if L[i] is a predecessor of L and
+    L[m-1-i] a successor of L, they are swapped.  Returns whether the roles
+    were swapped."""
+    keys = a[:, 0] if a.ndim == 2 else a
+    n = keys.shape[0]
+    rev = 2 * count_less(a, pivot) > n
+    L = a[::-1]
+    if not rev:
+        L = a
+    m = n
+    while m >= 2:
+        half = m // 2
+        lk = L[:, 0] if L.ndim == 2 else L
+        pred = lk.astype(np.uint64) < np.uint64(pivot)
+        if rev:
+            pred = ~pred
+        i = np.arange(half)
+        j = m - 1 - i
+        sw = pred[i] & ~pred[j]
+        ii, jj = i[sw], j[sw]
+        tmp = L[ii].copy()
+        L[ii] = L[jj]
+        L[jj] = tmp
+        m = (m + 1) // 2
+    return bool(rev)
+
+
 def sorted_sides(a: np.ndarray, split: int):
     """(sorted left side, sorted right side) -- the unique content of a partition.
 

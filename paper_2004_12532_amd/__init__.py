@@ -27,9 +27,9 @@ if not os.path.exists(_SO):
 _lib = ctypes.CDLL(_SO)
 
 SS_U32, SS_U64, SS_KV16 = 1, 2, 3
-SMOOTHED, STRIDED, LOWSPACE, HYBRID, MEDIUMSPACE, HIGHSPACE = 0, 1, 2, 3, 4, 5
+SMOOTHED, STRIDED, LOWSPACE, HYBRID, MEDIUMSPACE, HIGHSPACE, IMPLICIT = 0, 1, 2, 3, 4, 5, 6
 ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE, "hybrid": HYBRID,
-         "mediumspace": MEDIUMSPACE, "highspace": HIGHSPACE}
+         "mediumspace": MEDIUMSPACE, "highspace": HIGHSPACE, "implicit": IMPLICIT}
 FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH, FLAG_EXCHANGE, FLAG_EXCHANGE_SKEWED, FLAG_STABLE = \
     1, 2, 4, 8, 16, 32, 64, 128
 MAX_LEVELS = 32

@@ -160,7 +160,7 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     std::memset(&q, 0, sizeof(q));
     if (p)
         q = *p;
-    if (q.algo < SS_SMOOTHED || q.algo > SS_HIGHSPACE)
+    if (q.algo < SS_SMOOTHED || q.algo > SS_IMPLICIT)
         return fail_msg(SS_EINVAL, "unknown algo");
     if (q.flags &
         ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH | kExchangeFlags |
@@ -279,12 +279,12 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const Variant *V = pick_variant(dtype, R.engine, R.tile, (R.flags & SS_FLAG_STREAM) != 0);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
-    // The exchange table (half a group of 16-bit slot numbers) is dynamic LDS.
+    // The exchange tables (16-bit slot numbers) are dynamic LDS.
     const bool xch = (R.flags & kExchangeFlags) != 0;
     if (xch && !V->fn_x)
         return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
     int occ = 0;
-    rc = occupancy(dev, xch ? V->fn_x(true) : V->fn(true), V->nt, &occ, xch ? (size_t)V->tile / R.w : 0);
+    rc = occupancy(dev, xch ? V->fn_x(true) : V->fn(true), V->nt, &occ, xch ? xch_lds_bytes(V->tile, R.w) : 0);
     if (rc)
         return rc;
     uint32_t P = (uint32_t)(occ * cus);
@@ -301,7 +301,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     int occ_t = 0;
     if (xch && !Vt->fn_x)
         return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
-    rc = occupancy(dev, xch ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, &occ_t, xch ? (size_t)Vt->tile / R.w : 0);
+    rc = occupancy(dev, xch ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, &occ_t, xch ? xch_lds_bytes(Vt->tile, R.w) : 0);
     if (rc)
         return rc;
     uint32_t Pt = (uint32_t)(occ_t * cus);
@@ -325,7 +325,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         if (!Vx || !Vx->fn_x)
             return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
         int occ_x = 0;
-        rc = occupancy(dev, Vx->fn_x(true), Vx->nt, &occ_x, (size_t)Vx->tile / R.w);
+        rc = occupancy(dev, Vx->fn_x(true), Vx->nt, &occ_x, xch_lds_bytes(Vx->tile, R.w));
         if (rc)
             return rc;
         Px = (uint32_t)(occ_x * cus);
@@ -593,7 +593,7 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
     rc = resolve_params(p, dtype, &R, dtype == SS_U32 ? (uint32_t)SS_ENGINE_LDS : kDefaultEngine);
     if (rc)
         return rc;
-    if (R.algo == SS_LOWSPACE)
+    if (R.algo == SS_LOWSPACE || R.algo == SS_IMPLICIT)
         return lowspace_partition((char *)d_ptr, n, dtype, pivot, R, (hipStream_t)stream, d_split, h_split,
                                   stats);
     if (R.algo == SS_MEDIUMSPACE || R.algo == SS_HIGHSPACE)
@@ -686,6 +686,8 @@ size_t ss_aux_bytes(size_t n, int dtype, int algo)
                       sizeof(uint64_t);
     if (algo == SS_LOWSPACE || algo == SS_HYBRID)  // hybrid: Low-Space arrays for the middle region (< n)
         return ws + lowspace_aux_bytes(n);
+    if (algo == SS_IMPLICIT)
+        return ws + lowspace_aux_bytes(implicit_work_elems(n, dtype));
     if (algo == SS_MEDIUMSPACE || algo == SS_HIGHSPACE)
         return ws + prefix_aux_bytes(n, dtype, algo == SS_HIGHSPACE);
     return ws;

@@ -22,6 +22,8 @@ constexpr uint32_t kDefaultLevels = 8;
 constexpr uint32_t kExchangeFlags = SS_FLAG_EXCHANGE | SS_FLAG_EXCHANGE_SKEWED;
 constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a group's slots
 constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
+// LDS of the exchange form's slot table for groups of `tile` bytes of w-byte elements
+inline size_t xch_lds_bytes(uint32_t tile, int w) { return (size_t)tile / (uint32_t)w; }
 constexpr int kResultWritten = 6;   // result word: elements stored by exchange-form levels
 constexpr int kResultGate = 7;      // result word: 1 when the exchange form was chosen
 
@@ -156,6 +158,7 @@ uint64_t quicksort_leaf_cap(int dtype);
 int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                        uint64_t *d_split, size_t *h_split, ss_stats *stats);
 size_t lowspace_aux_bytes(size_t n);
+size_t implicit_work_elems(size_t n, int dtype);
 int prefix_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                      uint64_t *d_split, size_t *h_split, ss_stats *stats, bool explicit_prefix);
 size_t prefix_aux_bytes(size_t n, int dtype, bool explicit_prefix);

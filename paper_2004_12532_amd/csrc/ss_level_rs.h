@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             x.template load<false>(buf, i, m);
         return f;
     };
-    extern __shared__ uint16_t xt[];  // Ctx::XCH_SLOTS entries (exchange form)
+    extern __shared__ uint16_t xt[];  // Ctx::XCH_BYTES of exchange tables (exchange form)
     uint64_t written = 0;             // exchange form: elements this workgroup stored
     auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f, const Mask &m) -> uint32_t {
         if constexpr (XCH)
@@ -194,24 +194,30 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     }
 }
 
-// Launch of the stable form (XCH = false) or the exchange form (XCH = true),
-// whose table of slot numbers is dynamic LDS.
-template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
-hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
-{
-    const size_t shmem = XCH ? LevelCtx<T, NT, NV, NTMP>::XCH_SLOTS * sizeof(uint16_t) : 0;
-    if (first)
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
-    else
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
-    return hipGetLastError();
-}
-
 template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
 const void *level_rs_fn_t(bool first)
 {
     return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, NTMP, DB, XCH>)
                  : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, NTMP, DB, XCH>);
+}
+
+// Launch of the stable form (XCH = false) or the exchange form (XCH = true),
+// whose table of slot numbers is dynamic LDS.
+template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
+hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
+{
+    const size_t shmem = XCH ? LevelCtx<T, NT, NV, NTMP>::XCH_BYTES : 0;
+    if (shmem > 32768) {
+        const hipError_t e = hipFuncSetAttribute(level_rs_fn_t<T, NT, NV, NTMP, DB, XCH>(first),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess)
+            return e;
+    }
+    if (first)
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+    else
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+    return hipGetLastError();
 }
 
 // Every register-engine variant the host selects from: single buffer with

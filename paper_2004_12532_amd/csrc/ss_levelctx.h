@@ -236,7 +236,10 @@ struct LevelCtx {
     }
 
     // Slots of the exchange table: a group has at most S / 2 misplaced pairs.
+    // (A variant with two tables filled in one pass, saving two barriers per
+    // group, measured slower: 2.75 against 2.27 ms at 2^30 u64, q = 0.01.)
     static constexpr int XCH_SLOTS = NVEC * V / 2;
+    static constexpr size_t XCH_BYTES = XCH_SLOTS * sizeof(uint16_t);
 
     // Write-minimal partition of group i (the two-pointer exchange of the
     // serial step, Section 4): the k-th successor from the front of the slot

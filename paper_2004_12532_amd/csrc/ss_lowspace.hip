@@ -338,6 +338,476 @@ __global__ void __launch_bounds__(kNT) k_reorder_tail(Args a)
 }
 
 // ---------------------------------------------------------------------------
+// The fully implicit Blocked-Prefix-Sum partition (Section 3 as stated, the
+// Section 5.1 explicit block counts replaced by values kept in the order of
+// the elements themselves).  Steps 1-3 (counting, role swap, preprocessing)
+// are the Low-Space ones; then:
+//   4'. Blocks of kB = 256 elements (blocks X_0..X_{NB-1}, NB = floor(n/kB),
+//       the last one taking the n mod kB elements after it).  A block's first
+//       64 pairs (x_2j, x_2j+1) hold a value (Lemma bitstore): pair 0 marks
+//       the encoding and pair j >= 1 bit j-1.  Lemma bitstore2 (repeated
+//       elements): on the first write the block's 128 pairs are reordered so
+//       that its first 64 pairs are all unequal pairs (type 1: the bit is
+//       x_2j < x_2j+1, set by ordering the pair) or all equal pairs (type 2:
+//       the bit is x_2j != x_2j+1, set by flipping the lowest bit of x_2j+1 --
+//       of the payload for key-value records -- and undone when read).
+//       Pair 0 is unequal exactly for type 1.  Of 128 pairs at least 64 are of
+//       one kind, and 63 bits hold any count up to 2^40.  One wavefront reads
+//       or writes a value: one pair per lane, one ballot.
+//   4''. The prefix sum over the encoded values is done in place, level by
+//       level: level 1 counts every block and leaves in each block the
+//       inclusive prefix within its chunk of 256 blocks; level L > 1 scans
+//       the last blocks of the level-(L-1) chunks (entries of stride
+//       256^(L-1)) the same way, until one chunk remains; then, top down, each
+//       chunk adds the value of the entry before it to its other entries.
+//       The workgroup of a chunk holds 256 values in LDS at a time: memory
+//       per worker, not an array over the input.
+//   5'. Reordering as in step 5, with every block's prefix read from its own
+//       elements (and type-2 blocks restored) just before the block is used;
+//       the innermost prefix restores its blocks in LDS before partitioning.
+namespace ip {
+
+constexpr uint64_t kB = 256;     // elements per block
+constexpr int kChunk = 256;      // entries per workgroup in a scan level
+constexpr int kNT = 256;         // four wavefronts
+
+__device__ __forceinline__ bool el_lt(uint32_t a, uint32_t b) { return a < b; }
+__device__ __forceinline__ bool el_lt(uint64_t a, uint64_t b) { return a < b; }
+__device__ __forceinline__ bool el_lt(const KV &a, const KV &b)
+{
+    return a.key < b.key || (a.key == b.key && a.val < b.val);
+}
+__device__ __forceinline__ bool el_eq(uint32_t a, uint32_t b) { return a == b; }
+__device__ __forceinline__ bool el_eq(uint64_t a, uint64_t b) { return a == b; }
+__device__ __forceinline__ bool el_eq(const KV &a, const KV &b) { return a.key == b.key && a.val == b.val; }
+__device__ __forceinline__ uint32_t el_flip(uint32_t a) { return a ^ 1u; }
+__device__ __forceinline__ uint64_t el_flip(uint64_t a) { return a ^ 1ull; }
+__device__ __forceinline__ KV el_flip(const KV &a) { return KV{a.key, a.val ^ 1ull}; }
+
+// Lane l's value after exchanging T values across lanes (ds_bpermute per word).
+template <typename T>
+__device__ __forceinline__ T shfl_el(const T &v, int src)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized elements");
+    T out;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(&v);
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); k++)
+        o[k] = (uint32_t)__shfl((int)w[k], src, 64);
+    return out;
+}
+
+// Index of the i-th (0-based) set bit of m; m must have more than i set bits.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t i)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int half = 32; half >= 1; half >>= 1) {
+        const uint64_t low = m & ((half == 64 ? ~0ull : (1ull << half) - 1));
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (i >= c) {
+            i -= c;
+            m >>= half;
+            pos += half;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
+// The encode area of a block: pair `lane` = elements 2 lane, 2 lane + 1.
+template <typename T>
+struct Pair {
+    T a, b;
+};
+
+// Read the value held by the encode area (one pair per lane); restore type-2
+// pairs in registers (p.b = p.a) and report whether the lane's pair changed.
+template <typename T>
+__device__ __forceinline__ uint64_t decode(Pair<T> &p, int lane, bool &restored)
+{
+    const bool neq = !el_eq(p.a, p.b);
+    const bool type1 = __shfl((int)neq, 0, 64) != 0;
+    const uint64_t bits = type1 ? __ballot(el_lt(p.a, p.b)) : __ballot(neq);
+    restored = false;
+    if (!type1 && lane >= 1 && neq) {
+        p.b = p.a;
+        restored = true;
+    }
+    return bits >> 1;
+}
+
+// Write value v (< 2^63) into an encode area that already has its type (from
+// pair 0).  Returns whether this lane's pair changed; p holds the new pair.
+template <typename T>
+__device__ __forceinline__ bool encode(Pair<T> &p, int lane, uint64_t v)
+{
+    const bool type1 = __shfl((int)!el_eq(p.a, p.b), 0, 64) != 0;
+    if (lane == 0)
+        return false;
+    const bool bit = (v >> (lane - 1)) & 1;
+    if (type1) {
+        if (el_lt(p.a, p.b) != bit) {
+            const T t = p.a;
+            p.a = p.b;
+            p.b = t;
+            return true;
+        }
+        return false;
+    }
+    // type 2: the pair's two elements hold the same value, kept in p.a
+    const T want = bit ? el_flip(p.a) : p.a;
+    if (!el_eq(want, p.b)) {
+        p.b = want;
+        return true;
+    }
+    return false;
+}
+
+struct IpArgs {
+    ls::Args a;
+    uint64_t nb;        // blocks
+    uint64_t stride;    // blocks between entries of this scan level (256^(L-1))
+    uint64_t ne;        // entries of this scan level
+};
+
+// Block index of entry k of a scan level.
+__device__ __forceinline__ uint64_t entry_block(const IpArgs &g, uint64_t k)
+{
+    const uint64_t e = (k + 1) * g.stride;
+    return (e < g.nb ? e : g.nb) - 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pair(const ls::Args &a, bool rev, uint64_t blk, int lane, Pair<T> &p)
+{
+    const uint64_t x = blk * kB + 2 * (uint64_t)lane;
+    p.a = *ls::phys<T>(a, rev, x);
+    p.b = *ls::phys<T>(a, rev, x + 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pair(const ls::Args &a, bool rev, uint64_t blk, int lane, const Pair<T> &p)
+{
+    const uint64_t x = blk * kB + 2 * (uint64_t)lane;
+    *ls::phys<T>(a, rev, x) = p.a;
+    *ls::phys<T>(a, rev, x + 1) = p.b;
+}
+
+// Workgroup-inclusive scan of vals[kChunk] in LDS (kNT = kChunk threads).
+__device__ __forceinline__ void chunk_scan(uint64_t *vals, uint64_t *wsum)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t x = vals[threadIdx.x];
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, 64);
+        if (lane >= d)
+            inc += y;
+    }
+    if (lane == 63)
+        wsum[wid] = inc;
+    __syncthreads();
+    uint64_t off = 0;
+    for (int w = 0; w < wid; w++)
+        off += wsum[w];
+    vals[threadIdx.x] = off + inc;
+    __syncthreads();
+}
+
+// Scan level 1: count every block of L (the last one with its extra
+// elements), give its first 64 pairs one kind (first write of Lemma
+// bitstore2), and leave the inclusive prefix within the chunk of 256 blocks.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ip_level1(IpArgs g)
+{
+    __shared__ uint64_t vals[kChunk];
+    __shared__ uint64_t wsum[kNT / 64];
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    for (int k = wid; k < kChunk; k += kNT / 64) {
+        const uint64_t blk = c0 + k;
+        uint64_t cnt = 0;
+        if (blk < g.nb) {
+            // pairs `lane` (front) and `lane + 64` (back) of the block
+            Pair<T> f, bk;
+            load_pair(a, rev, blk, lane, f);
+            load_pair(a, rev, blk, lane + 64, bk);
+            const uint64_t pv = a.pivot;
+            auto pred = [&](const T &v) { return ls::is_pred(v, pv) != rev; };
+            cnt = (uint64_t)__popcll(__ballot(pred(f.a))) + __popcll(__ballot(pred(f.b))) +
+                  __popcll(__ballot(pred(bk.a))) + __popcll(__ballot(pred(bk.b)));
+            if (blk == g.nb - 1) {
+                // the last block's elements after its first kB
+                for (uint64_t x0 = (blk + 1) * kB; x0 < a.n; x0 += 64) {
+                    const uint64_t x = x0 + lane;
+                    cnt += __popcll(__ballot(x < a.n && pred(*ls::phys<T>(a, rev, x))));
+                }
+            }
+            // Lemma bitstore2, first write: the majority kind of pair to the front 64 slots
+            const bool uf = !el_eq(f.a, f.b), ub = !el_eq(bk.a, bk.b);
+            const uint64_t mf = __ballot(uf), mb = __ballot(ub);
+            const bool type1 = __popcll(mf) + __popcll(mb) >= 64;
+            const uint64_t good_f = type1 ? mf : ~mf, good_b = type1 ? mb : ~mb;
+            const uint64_t bad_f = ~good_f;
+            if (bad_f) {
+                // the i-th front pair of the other kind swaps with the i-th back pair of this kind
+                const bool fb = (bad_f >> lane) & 1, bg = (good_b >> lane) & 1;
+                const uint32_t rf = (uint32_t)__popcll(bad_f & ((1ull << lane) - 1));
+                const uint32_t rb = (uint32_t)__popcll(good_b & ((1ull << lane) - 1));
+                const int src_for_front = fb ? (int)nth_set_bit(good_b, rf) : lane;
+                const int src_for_back = bg && rb < (uint32_t)__popcll(bad_f) ? (int)nth_set_bit(bad_f, rb) : lane;
+                const T na = shfl_el(bk.a, src_for_front), nb = shfl_el(bk.b, src_for_front);
+                const T ba = shfl_el(f.a, src_for_back), bb = shfl_el(f.b, src_for_back);
+                if (fb) {
+                    f.a = na;
+                    f.b = nb;
+                    store_pair(a, rev, blk, lane, f);
+                }
+                if (bg && rb < (uint32_t)__popcll(bad_f)) {
+                    bk.a = ba;
+                    bk.b = bb;
+                    store_pair(a, rev, blk, lane + 64, bk);
+                }
+            }
+        }
+        if (lane == 0)
+            vals[k] = cnt;
+    }
+    __syncthreads();
+    chunk_scan(vals, wsum);
+    for (int k = wid; k < kChunk; k += kNT / 64) {
+        const uint64_t blk = c0 + k;
+        if (blk >= g.nb)
+            break;
+        Pair<T> f;
+        load_pair(a, rev, blk, lane, f);
+        if (encode(f, lane, vals[k]))
+            store_pair(a, rev, blk, lane, f);
+    }
+}
+
+// Scan level L > 1 over entries of stride g.stride: decode, scan the chunk,
+// encode the inclusive prefixes.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ip_up(IpArgs g)
+{
+    __shared__ uint64_t vals[kChunk];
+    __shared__ uint64_t wsum[kNT / 64];
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    for (int k = wid; k < kChunk; k += kNT / 64) {
+        uint64_t v = 0;
+        if (c0 + k < g.ne) {
+            Pair<T> f;
+            load_pair(a, rev, entry_block(g, c0 + k), lane, f);
+            bool r;
+            v = decode(f, lane, r);
+        }
+        if (lane == 0)
+            vals[k] = v;
+    }
+    __syncthreads();
+    chunk_scan(vals, wsum);
+    for (int k = wid; k < kChunk; k += kNT / 64) {
+        if (c0 + k >= g.ne)
+            break;
+        const uint64_t blk = entry_block(g, c0 + k);
+        Pair<T> f;
+        load_pair(a, rev, blk, lane, f);
+        bool r;
+        (void)decode(f, lane, r);  // restores type-2 pairs in registers before re-encoding
+        if (encode(f, lane, vals[k]) || r)
+            store_pair(a, rev, blk, lane, f);
+    }
+}
+
+// Down-sweep of level L: chunk c > 0 adds the (global) value of the entry
+// before it to its entries except its last one.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ip_down(IpArgs g)
+{
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t c = (uint64_t)blockIdx.x + 1;
+    const uint64_t c0 = c * kChunk;
+    if (c0 >= g.ne)
+        return;
+    uint64_t off;
+    {
+        Pair<T> f;
+        load_pair(a, rev, entry_block(g, c0 - 1), lane, f);
+        bool r;
+        off = decode(f, lane, r);
+    }
+    const uint64_t last = (c0 + kChunk < g.ne ? c0 + kChunk : g.ne) - 1;
+    for (uint64_t k = c0 + wid; k < last; k += kNT / 64) {
+        const uint64_t blk = entry_block(g, k);
+        Pair<T> f;
+        load_pair(a, rev, blk, lane, f);
+        bool r;
+        const uint64_t v = decode(f, lane, r);
+        if (encode(f, lane, v + off) || r)
+            store_pair(a, rev, blk, lane, f);
+    }
+}
+
+// After the top level: the predecessor count of L is the last block's value.
+template <typename T>
+__global__ void __launch_bounds__(64) k_ip_total(IpArgs g)
+{
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const int lane = threadIdx.x;
+    Pair<T> f;
+    load_pair(a, rev, g.nb - 1, lane, f);
+    bool r;
+    const uint64_t cl = decode(f, lane, r);
+    if (lane == 0) {
+        const uint64_t split = rev ? a.n - cl : cl;
+        a.ctl[2] = cl;
+        a.ctl[3] = split;
+        if (a.d_split)
+            *a.d_split = split;
+        if (a.host) {
+            a.host[0] = 1;
+            a.host[1] = split;
+            a.host[2] = a.ctl[0];
+            a.host[3] = rev;
+        }
+    }
+}
+
+// Reordering, one tail: blocks [lo_blk, hi_blk) of L, one wavefront per
+// block.  The block's inclusive prefix is read from (and type-2 pairs are
+// restored in) its encode area; its j-th predecessor then swaps with L[r],
+// r = prefix - count + j, a successor in the partitioned prefix.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_ip_tail(IpArgs g)
+{
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (kNT / 64);
+    const uint64_t pv = a.pivot;
+    for (uint64_t blk = a.lo_blk + (uint64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6); blk < a.hi_blk;
+         blk += waves) {
+        Pair<T> f;
+        load_pair(a, rev, blk, lane, f);
+        bool restored;
+        const uint64_t incl = decode(f, lane, restored);
+        if (restored)
+            *ls::phys<T>(a, rev, blk * kB + 2 * (uint64_t)lane + 1) = f.b;
+        const uint64_t end = blk == g.nb - 1 ? a.n : (blk + 1) * kB;
+        // count the block's predecessors (elements 0..127 are in f, the rest are read)
+        uint64_t cnt = (uint64_t)__popcll(__ballot(ls::is_pred(f.a, pv) != rev)) +
+                       __popcll(__ballot(ls::is_pred(f.b, pv) != rev));
+        for (uint64_t x = blk * kB + 128 + lane; x - lane < end; x += 64) {
+            const bool p = x < end && (ls::is_pred(*ls::phys<T>(a, rev, x), pv) != rev);
+            cnt += __popcll(__ballot(p));
+        }
+        uint64_t r = incl - cnt;
+        // the encode area: element 2 lane then 2 lane + 1, in element order
+        {
+            const bool p0 = ls::is_pred(f.a, pv) != rev, p1 = ls::is_pred(f.b, pv) != rev;
+            const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
+            const uint64_t below = lanes_below(m0) + lanes_below(m1);
+            const uint64_t x0 = blk * kB + 2 * (uint64_t)lane;
+            uint64_t rr = r + below;
+            // every target lies in the partitioned prefix [0, lo_blk kB); the
+            // bound is implied by the prefix values and kept as a guard
+            const uint64_t lim = a.lo_blk * kB;
+            if (p0 && rr < lim) {
+                T *dst = ls::phys<T>(a, rev, rr);
+                const T w = *dst;
+                *dst = f.a;
+                *ls::phys<T>(a, rev, x0) = w;
+                rr++;
+            }
+            if (p1 && rr < lim) {
+                T *dst = ls::phys<T>(a, rev, rr);
+                const T w = *dst;
+                *dst = f.b;
+                *ls::phys<T>(a, rev, x0 + 1) = w;
+            }
+            r += __popcll(m0) + __popcll(m1);
+        }
+        for (uint64_t x0 = blk * kB + 128; x0 < end; x0 += 64) {
+            const uint64_t x = x0 + lane;
+            bool p = false;
+            T v;
+            if (x < end) {
+                v = *ls::phys<T>(a, rev, x);
+                p = ls::is_pred(v, pv) != rev;
+            }
+            const uint64_t m = __ballot(p);
+            if (p && r + lanes_below(m) < a.lo_blk * kB) {
+                T *dst = ls::phys<T>(a, rev, r + lanes_below(m));
+                const T w = *dst;
+                *dst = v;
+                *ls::phys<T>(a, rev, x) = w;
+            }
+            r += __popcll(m);
+        }
+    }
+}
+
+// Reordering, innermost prefix L[0, m) (m a multiple of kB, at most one LDS
+// buffer): restore the type-2 blocks in LDS, then partition stably.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_ip_base(IpArgs g)
+{
+    constexpr int CAP = ls::kSmallBytes / sizeof(T);
+    constexpr int K = CAP / 1024;
+    __shared__ T buf[CAP];
+    __shared__ uint32_t sh[K * 16 + 1];
+    const ls::Args &a = g.a;
+    const bool rev = a.ctl[1] != 0;
+    const uint32_t m = (uint32_t)a.m;
+    for (uint32_t k = threadIdx.x; k < m; k += 1024)
+        buf[k] = *ls::phys<T>(a, rev, k);
+    __syncthreads();
+    // type-2 blocks: pair 0 equal; pairs 1..63 restore x_2j+1 = x_2j
+    for (uint32_t k = threadIdx.x; k < (m / (uint32_t)kB) * 64; k += 1024) {
+        const uint32_t blk = k / 64, j = k % 64;
+        if (j >= 1 && el_eq(buf[blk * kB], buf[blk * kB + 1]))
+            buf[blk * kB + 2 * j + 1] = buf[blk * kB + 2 * j];
+    }
+    __syncthreads();
+    T x[K];
+    bool f[K];
+    uint32_t rk[K], tot;
+    for (int r = 0; r < K; r++) {
+        const uint32_t k = r * 1024 + threadIdx.x;
+        f[r] = false;
+        if (k < m) {
+            x[r] = buf[k];
+            f[r] = ls::is_pred(x[r], a.pivot) != rev;
+        }
+    }
+    __syncthreads();
+    block_rank<1024, K>(f, rk, tot, sh);
+    for (int r = 0; r < K; r++) {
+        const uint32_t k = r * 1024 + threadIdx.x;
+        if (k < m)
+            buf[f[r] ? rk[r] : tot + k - rk[r]] = x[r];
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += 1024)
+        *ls::phys<T>(a, rev, k) = buf[k];
+}
+
+}  // namespace ip
+
+// ---------------------------------------------------------------------------
 // The Medium- and High-Space comparators (Section 5.1): the standard parallel
 // partition with an n-sized output array.  The predecessor counts of blocks
 // of 64 elements and their prefix sums are formed as above (with the roles
@@ -427,6 +897,13 @@ constexpr uint32_t kPartMax = 4096;
 
 }  // namespace
 
+// Elements for which the implicit variant sizes the Low-Space work arrays.
+size_t implicit_work_elems(size_t n, int dtype)
+{
+    const size_t small = ls::kSmallBytes / (size_t)elem_size(dtype);
+    return n < small ? n : small;
+}
+
 size_t lowspace_aux_bytes(size_t n)
 {
     const size_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
@@ -434,9 +911,71 @@ size_t lowspace_aux_bytes(size_t n)
     return nblk * sizeof(uint32_t) + nwg * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + 8 * sizeof(uint64_t);
 }
 
+// Steps 4'-5' of the implicit variant (after steps 1-3 on n > one LDS buffer).
+// With stop_after_sum the call ends once every block holds its prefix.
+template <typename T>
+static void implicit_steps(const ls::Args &a0, hipStream_t st, uint64_t stream_grid, uint32_t *launches,
+                           bool stop_after_sum)
+{
+    ls::ip::IpArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.a = a0;
+    g.nb = a0.n / ls::ip::kB;
+    auto chunks = [](uint64_t ne) { return (ne + ls::ip::kChunk - 1) / ls::ip::kChunk; };
+    // up-sweep: level 1 over every block, then the last blocks of the chunks
+    std::vector<std::pair<uint64_t, uint64_t>> lv;  // (stride, entries) per level
+    g.stride = 1;
+    g.ne = g.nb;
+    lv.push_back({g.stride, g.ne});
+    hipLaunchKernelGGL(ls::ip::k_ip_level1<T>, dim3((uint32_t)chunks(g.ne)), dim3(ls::ip::kNT), 0, st, g);
+    (*launches)++;
+    while (g.ne > (uint64_t)ls::ip::kChunk) {
+        g.stride *= ls::ip::kChunk;
+        g.ne = (g.nb + g.stride - 1) / g.stride;
+        lv.push_back({g.stride, g.ne});
+        hipLaunchKernelGGL(ls::ip::k_ip_up<T>, dim3((uint32_t)chunks(g.ne)), dim3(ls::ip::kNT), 0, st, g);
+        (*launches)++;
+    }
+    hipLaunchKernelGGL(ls::ip::k_ip_total<T>, dim3(1), dim3(64), 0, st, g);
+    (*launches)++;
+    // down-sweep, top level first
+    for (size_t L = lv.size() - 1; L-- > 0;) {
+        g.stride = lv[L].first;
+        g.ne = lv[L].second;
+        const uint64_t c = chunks(g.ne);
+        if (c > 1) {
+            hipLaunchKernelGGL(ls::ip::k_ip_down<T>, dim3((uint32_t)(c - 1)), dim3(ls::ip::kNT), 0, st, g);
+            (*launches)++;
+        }
+    }
+    if (stop_after_sum)
+        return;
+    // reorder: prefixes N_0 = n > N_1 > ... > N_K <= one LDS buffer, each a whole number of blocks
+    const uint64_t small = ls::kSmallBytes / sizeof(T);
+    std::vector<uint64_t> N{a0.n};
+    while (N.back() > small) {
+        const uint64_t cur = N.back();
+        const uint64_t t = (4 * cur / 5) / ls::ip::kB + 1;  // least t with t * kB > 4 cur / 5
+        N.push_back(t * ls::ip::kB);
+    }
+    g.a.m = N.back();
+    hipLaunchKernelGGL(ls::ip::k_ip_base<T>, dim3(1), dim3(1024), 0, st, g);
+    (*launches)++;
+    for (size_t k = N.size() - 1; k-- > 0;) {
+        g.a.lo_blk = N[k + 1] / ls::ip::kB;
+        g.a.hi_blk = k == 0 ? g.nb : N[k] / ls::ip::kB;
+        const uint64_t waves_needed = g.a.hi_blk - g.a.lo_blk;
+        uint64_t gr = (waves_needed + (ls::ip::kNT / 64) - 1) / (ls::ip::kNT / 64);
+        if (gr > stream_grid)
+            gr = stream_grid;
+        hipLaunchKernelGGL(ls::ip::k_ip_tail<T>, dim3((uint32_t)(gr ? gr : 1)), dim3(ls::ip::kNT), 0, st, g);
+        (*launches)++;
+    }
+}
+
 template <typename T>
 static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, uint64_t *d_split, Workspace *ws,
-                        LsWork &w, int cus, uint32_t *launches, bool pre_only)
+                        LsWork &w, int cus, uint32_t *launches, bool pre_only, bool implicit)
 {
     hipError_t e;
     ls::Args a;
@@ -479,9 +1018,16 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
         hipLaunchKernelGGL(ls::k_pre_small<T>, dim3(1), dim3(1024), 0, st, a);
         (*launches)++;
     }
-    if (pre_only) {
+    if (pre_only && !implicit) {
         if ((e = hipGetLastError()) != hipSuccess)
             return fail_device(e, "Low-Space kernel launch");
+        return SS_OK;
+    }
+    if (implicit && n > small) {
+        // 4'-5'. values kept in the blocks' element order (with pre_only: stop after the prefix sum)
+        implicit_steps<T>(a, st, stream_grid, launches, pre_only);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail_device(e, "implicit Blocked-Prefix-Sum kernel launch");
         return SS_OK;
     }
     // 4. block counts and prefix sums
@@ -561,8 +1107,12 @@ int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Re
     rc = get_workspace(dev, st, &ws);
     if (rc)
         return rc;
+    // The implicit variant keeps no block arrays: only arrays of at most one
+    // LDS buffer, which it partitions with the explicit steps, use them.
+    const bool implicit = R.algo == SS_IMPLICIT;
+    const size_t nw = implicit ? implicit_work_elems(n, dtype) : n;
     LsWork *w = nullptr;
-    if ((rc = ls_work(dev, st, n, &w)))
+    if ((rc = ls_work(dev, st, nw, &w)))
         return rc;
     RunOut ro;
     std::memset(&ro, 0, sizeof(ro));
@@ -574,9 +1124,12 @@ int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Re
             return fail_device(e, "hipEventRecord");
         const bool pre_only = (R.flags & SS_FLAG_ONE_LEVEL) != 0;
         switch (dtype) {
-        case SS_U32: rc = lowspace_run<uint32_t>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only); break;
-        case SS_U64: rc = lowspace_run<uint64_t>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only); break;
-        default: rc = lowspace_run<KV>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only); break;
+        case SS_U32: rc = lowspace_run<uint32_t>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only, implicit);
+            break;
+        case SS_U64: rc = lowspace_run<uint64_t>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only, implicit);
+            break;
+        default: rc = lowspace_run<KV>(base, n, pivot, st, d_split, ws, *w, cus, &ro.launches, pre_only, implicit);
+            break;
         }
         if (rc)
             return rc;
@@ -591,7 +1144,7 @@ int lowspace_partition(char *base, size_t n, int dtype, uint64_t pivot, const Re
     ro.split = n ? hres[1] : 0;
     ro.done = n ? hres[0] != 0 : true;
     const uint64_t pred_count = n ? hres[2] : 0, reversed = n ? hres[3] : 0;
-    ro.aux_bytes = ws->bytes + lowspace_aux_bytes(n);
+    ro.aux_bytes = ws->bytes + lowspace_aux_bytes(nw);
     if (R.flags & SS_FLAG_TIME && n) {
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ws->ev[0], ws->ev[1]);

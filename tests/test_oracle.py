@@ -322,3 +322,50 @@ def test_partial_step_rejects_bad_geometry():
         oracle.ss_partial_step(a, 4, 5, 6, np.zeros(6, np.uint32), 1)  # padding spans a chunk
     with pytest.raises(ValueError):
         oracle.ss_partial_step(a, 4, 5, 5, np.full(5, 5, np.uint32), 1)  # X_j >= g
+
+
+def _succ_heavy_prefixes(L, pivot, rev):
+    keys = L[:, 0] if L.ndim == 2 else L
+    succ = (keys.astype(np.uint64) < np.uint64(pivot)) if rev else (keys.astype(np.uint64) >= np.uint64(pivot))
+    c = np.cumsum(succ.astype(np.int64))
+    return (4 * c >= np.arange(1, len(keys) + 1)).all()
+
+
+def test_make_successor_heavy_lemma_random():
+    """Lemma preprocessingphase: every prefix of the logical array holds at least a
+    quarter successors afterwards; the multiset is unchanged; the roles are swapped
+    exactly when predecessors are the majority."""
+    rng = np.random.default_rng(21)
+    for n in (1, 2, 3, 7, 64, 1000, 4097, 65537):
+        for q in (0.0, 0.05, 0.3, 0.5, 0.7, 0.95, 1.0):
+            a = rng.integers(0, 1 << 62, size=n, dtype=np.uint64)
+            pivot = int(np.quantile(a, q)) + (1 if q == 1.0 else 0)
+            b = a.copy()
+            rev = oracle.make_successor_heavy(b, pivot)
+            assert rev == (2 * oracle.count_less(a, pivot) > n)
+            assert oracle.fingerprint(b) == oracle.fingerprint(a)
+            L = b[::-1] if rev else b
+            assert _succ_heavy_prefixes(L, pivot, rev), (n, q)
+
+
+def test_make_successor_heavy_exhaustive_small_and_kv():
+    """All arrays of length <= 6 over {0..3} with every pivot; the lemma fails for
+    some of these inputs before the phase (so the phase is doing work)."""
+    failed_before = 0
+    for n in range(1, 7):
+        for tup in itertools.product(range(4), repeat=n):
+            a = np.array(tup, dtype=np.uint64)
+            for pivot in range(5):
+                rev = 2 * oracle.count_less(a, pivot) > n
+                if not _succ_heavy_prefixes(a[::-1] if rev else a, pivot, rev):
+                    failed_before += 1
+                b = a.copy()
+                assert oracle.make_successor_heavy(b, pivot) == rev
+                assert sorted(b.tolist()) == sorted(a.tolist())
+                assert _succ_heavy_prefixes(b[::-1] if rev else b, pivot, rev), (tup, pivot)
+    assert failed_before > 0
+    kv = np.stack([np.arange(1000, dtype=np.uint64)[::-1] % 37, np.arange(1000, dtype=np.uint64)], axis=1).copy()
+    b = kv.copy()
+    rev = oracle.make_successor_heavy(b, 10)
+    assert oracle.fingerprint(b) == oracle.fingerprint(kv)
+    assert _succ_heavy_prefixes(b[::-1] if rev else b, 10, rev)
