@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             x.template load<false>(buf, i, m);
         return f;
     };
-    extern __shared__ uint16_t xt[];  // Ctx::XCH_BYTES of exchange tables (exchange form)
+    extern __shared__ uint16_t xt[];  // Ctx::XCH_BYTES: the exchange table (exchange form)
     uint64_t written = 0;             // exchange form: elements this workgroup stored
     auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f, const Mask &m) -> uint32_t {
         if constexpr (XCH)
