@@ -78,6 +78,7 @@ class Job:
     arrival: float       # seconds since the start of the run
     quantile: float = 0.5
     pivot: int = 0       # partition jobs: key < pivot
+    cancel_at: float = -1.0  # >= 0: the client withdraws the job at this time (seconds from the start)
     # runtime state
     off: int = -1
     block: int = 0
@@ -86,6 +87,7 @@ class Job:
     admitted: float = -1.0
     done: float = -1.0
     split: int = -1
+    status: str = "pending"  # then "done", "rejected" (can never fit the budget) or "cancelled"
 
     @property
     def latency(self) -> float:
@@ -105,6 +107,12 @@ def make_jobs(count: int, rate_per_s: float, seed: int, p_partition: float = 0.7
                         seed=(seed << 20) ^ k, arrival=float(arr[k]), quantile=q,
                         pivot=min(U64MASK, int(q * (1 << 64)))))
     return jobs
+
+
+def never_fits(n: int, aux: int, capacity: int, aux_budget: int) -> bool:
+    """A job of n records and `aux` auxiliary bytes cannot be admitted even by an
+    idle server: it is rejected at arrival instead of waiting forever."""
+    return n > capacity or aux > aux_budget
 
 
 class Server:
@@ -156,10 +164,16 @@ class Server:
 
     def _finish(self, job: Job, now: float, split: int):
         job.done = now
-        if job.kind == "partition":
-            job.split = split
-        if self.keep_outputs:
-            self.outputs[job.job_id] = self.arena_t[job.off:job.off + job.n].cpu().numpy().view(np.uint64).copy()
+        if job.status == "cancelled":
+            # withdrawn while on the device: its work ran to the end of a tick; the result is dropped
+            pass
+        else:
+            job.status = "done"
+            if job.kind == "partition":
+                job.split = split
+            if self.keep_outputs:
+                self.outputs[job.job_id] = \
+                    self.arena_t[job.off:job.off + job.n].cpu().numpy().view(np.uint64).copy()
         self.arena.release(job.off, job.block)
         self.free_slots.append(job.slot)
         self.aux_used -= job.aux
@@ -177,13 +191,25 @@ class Server:
         while qi < len(pending) or waiting or active:
             now = time.perf_counter() - t0
             while qi < len(pending) and (not realtime or pending[qi].arrival <= now):
-                waiting.append(pending[qi])
+                job = pending[qi]
                 qi += 1
+                kind = 0 if job.kind == "partition" else 1
+                if never_fits(job.n, server_job_aux_bytes(SS_KV16, kind, job.n), self.capacity, self.aux_budget):
+                    job.status, job.done = "rejected", now
+                    continue
+                waiting.append(job)
+            # withdrawals: a waiting job leaves the queue, an admitted one has its result dropped
+            for job in [j for j in waiting if 0 <= j.cancel_at <= now]:
+                waiting.remove(job)
+                job.status, job.done = "cancelled", now
+            for job in active:
+                if 0 <= job.cancel_at <= now:
+                    job.status = "cancelled"
             # FIFO admission while the budget has room
             while waiting and self._admit(waiting[0], t0):
                 active.append(waiting.pop(0))
-            if waiting and not active:
-                raise RuntimeError("job %d (%d records) does not fit the memory budget"
+            if waiting and not active:  # cannot happen: jobs that never fit were rejected
+                raise RuntimeError("job %d (%d records) was not admitted by an idle server"
                                    % (waiting[0].job_id, waiting[0].n))
             if not active:
                 if qi < len(pending):
@@ -211,6 +237,8 @@ class Server:
 
 
 def latency_summary(jobs: list) -> dict:
+    """Latency and throughput over the jobs that completed (rejected and cancelled ones excluded)."""
+    jobs = [j for j in jobs if j.status == "done"]
     lat = np.array([j.latency for j in jobs]) * 1e3
     recs = sum(j.n for j in jobs)
     span = max(j.done for j in jobs) - min(j.arrival for j in jobs)

@@ -107,3 +107,26 @@ def test_engine_direct_jobs_and_capacity_flag(ss):
     assert eng.status() & 1
     assert sum(eng.done(k)[0] for k in range(5)) == 4
     eng.close()
+
+
+def test_serving_rejects_oversized_and_cancels(ss):
+    """A job that can never fit the budget is rejected at arrival; withdrawn jobs
+    (waiting, or already on the device) end as cancelled without a result; the
+    rest are served correctly and every resource is returned."""
+    from paper_2004_12532_amd.serving import Job, make_jobs, latency_summary
+    jobs = make_jobs(12, 0.0, 31, lo_log2=12.0, hi_log2=17.0)
+    srv = _server(ss, budget=256 << 20)
+    big = Job(job_id=100, kind="partition", n=srv.capacity + 1, seed=7, arrival=0.0, pivot=1 << 63)
+    jobs[3].cancel_at = 0.0                     # withdrawn before it can be admitted
+    # a long sort withdrawn shortly after its admission: its ticks run, its result is dropped
+    late = Job(job_id=101, kind="sort", n=1 << 21, seed=8, arrival=0.0, cancel_at=5e-4)
+    srv.run(jobs + [big, late], realtime=False)
+    assert big.status == "rejected"
+    assert jobs[3].status == "cancelled" and jobs[3].admitted < 0 and jobs[3].job_id not in srv.outputs
+    assert late.status == "cancelled" and late.admitted >= 0 and late.job_id not in srv.outputs
+    for job in jobs:
+        if job.status == "done":
+            _check_job(job, srv.outputs[job.job_id])
+    assert sum(j.status == "done" for j in jobs) == 11
+    assert srv.arena.used == 0 and srv.aux_used == 0 and len(srv.free_slots) == 4096
+    assert latency_summary(jobs + [big, late])["jobs"] == 11

@@ -57,3 +57,12 @@ def test_job_mix_shape():
     arr = np.array([j.arrival for j in jobs])
     assert np.all(np.diff(arr) >= 0)
     assert abs(len(jobs) / arr[-1] - 100.0) < 8.0  # Poisson rate
+
+
+def test_never_fits_rule():
+    m = _arena()
+    assert not m.never_fits(100, 1000, capacity=100, aux_budget=1000)     # exactly at the limits
+    assert m.never_fits(101, 10, capacity=100, aux_budget=1000)           # more records than the arena
+    assert m.never_fits(10, 1001, capacity=100, aux_budget=1000)          # more auxiliary state than budgeted
+    j = m.Job(job_id=1, kind="sort", n=5, seed=1, arrival=0.0)
+    assert j.status == "pending" and j.cancel_at < 0
