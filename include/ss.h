@@ -118,7 +118,9 @@ enum ss_status {
                                   successors, reported in ss_stats (Section 4).  With SS_LOWSPACE:
                                   stop after the preprocessing phase (Section 3); ss_stats.vmin is
                                   then the predecessor count and ss_stats.vmax is 1 if the roles
-                                  were swapped (the array is read reversed).  For tests. */
+                                  were swapped (the array is read reversed).  With SS_IMPLICIT
+                                  (above 64 KiB): stop once every block holds its prefix.  For
+                                  tests. */
 #define SS_FLAG_TIME 2u        /* time the first-level kernel and the whole call with HIP events on
                                   the call's stream; reported in ss_stats (synchronizes). */
 #define SS_FLAG_STREAM 4u      /* register engines: non-temporal (streaming) loads and stores */
@@ -139,13 +141,13 @@ enum ss_status {
 #define SS_FLAG_STABLE 128u    /* never use the exchange form (see below) */
 /* Without SS_FLAG_EXCHANGE, SS_FLAG_EXCHANGE_SKEWED or SS_FLAG_STABLE, a
  * Smoothed Striding, Strided or Hybrid call on at least 2^22 elements of 8 or
- * 16 bytes with default engine, b and tile_bytes chooses the form of its first
- * level from a sample of 4096 keys at fixed positions (64 runs of 64 keys
- * spread evenly over the array): the exchange form
- * with 32768-byte groups when at most 1/16 (8-byte keys) or 1/10 (16-byte
- * records) of them, or at least 15/16 or 9/10, are predecessors, else the
- * stable form.  The choice depends only on the input,
- * so a call stays deterministic; ss_stats.exchange_levels reports it. */
+ * 16 bytes, with default engine, b and tile_bytes, chooses the form of its
+ * first level from a sample of 4096 keys at fixed positions (64 runs of 64 keys
+ * spread evenly over the array).  It takes the exchange form with 32768-byte
+ * groups when at most 1/16 (8-byte keys) or 1/10 (16-byte records) of the
+ * sample, or at least 15/16 or 9/10, are predecessors; else the stable form.
+ * The choice depends only on the input, so a call stays deterministic;
+ * ss_stats.exchange_levels reports it. */
 
 /* Tuning parameters; a zero field means "choose automatically". */
 typedef struct ss_params {
