@@ -62,7 +62,16 @@ struct Args {
     uint64_t lo_blk, hi_blk;  // reorder tail blocks [lo_blk, hi_blk)
     uint64_t *d_split;
     uint64_t *host;       // mapped host memory for the result (nullable)
+    uint32_t whole;       // store whole vectors and blocks, changed or not (arrays far above the
+                          // 256 MiB last-level cache, see kWholeLineBytes)
 };
+
+// Above this many bytes an array's passes store whole vectors and blocks, so
+// that HBM sees whole lines: the top level at 2^30 u64 took 4.35 ms with only
+// the changed vectors stored and 3.7 ms with all of them.  Smaller arrays
+// (a Hybrid call's middle region) mostly stay in the 256 MiB Infinity Cache,
+// which absorbs partial lines, and there the extra stores only cost time.
+constexpr uint64_t kWholeLineBytes = 512ull << 20;
 
 template <typename T>
 __device__ __forceinline__ T *phys(const Args &a, bool rev, uint64_t x)
@@ -121,6 +130,7 @@ __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_
             const uint64_t t = t0 + u * stride;
             if (t >= nvec)
                 break;
+            bool any = false;
 #pragma unroll
             for (int e = 0; e < V; e++) {
                 // logical front element V t + e and its partner m - 1 - V t - e
@@ -133,14 +143,13 @@ __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_
                     const T tmp = x;
                     x = y;
                     y = tmp;
+                    any = true;
                 }
             }
-            // every vector is stored, changed or not: whole lines are written,
-            // which HBM takes faster than the scattered partial lines of the
-            // swapped vectors alone (measured: 4.35 ms for the top level at
-            // 2^30 u64 with only the changed vectors stored)
-            *reinterpret_cast<v4u *>(base + front_at(t) * sizeof(T)) = f[u].v;
-            *reinterpret_cast<v4u *>(base + back_at(t) * sizeof(T)) = b[u].v;
+            if (a.whole || any) {
+                *reinterpret_cast<v4u *>(base + front_at(t) * sizeof(T)) = f[u].v;
+                *reinterpret_cast<v4u *>(base + back_at(t) * sizeof(T)) = b[u].v;
+            }
         }
     }
     // the last pairs, x in [V nvec, half), one per thread of workgroup 0
@@ -415,8 +424,8 @@ __global__ void __launch_bounds__(kNT) k_reorder_tail(Args a)
                 *dst = v[u];
                 v[u] = w;
             }
-            if (x < a.n)
-                *phys<T>(a, rev, x) = v[u];  // the whole block, so that its lines are written whole
+            if (x < a.n && (a.whole || p[u]))
+                *phys<T>(a, rev, x) = v[u];
         }
     }
 }
@@ -671,8 +680,8 @@ __global__ void __launch_bounds__(kNT) k_ip_level1(IpArgs g)
             break;
         Pair<T> f;
         load_pair(a, rev, blk, lane, f);
-        if (encode(f, lane, vals[k]))
-            store_pair(a, rev, blk, lane, f);
+        (void)encode(f, lane, vals[k]);
+        store_pair(a, rev, blk, lane, f);  // the whole encode area: whole lines are written
     }
 }
 
@@ -708,8 +717,8 @@ __global__ void __launch_bounds__(kNT) k_ip_up(IpArgs g)
         load_pair(a, rev, blk, lane, f);
         bool r;
         (void)decode(f, lane, r);  // restores type-2 pairs in registers before re-encoding
-        if (encode(f, lane, vals[k]) || r)
-            store_pair(a, rev, blk, lane, f);
+        (void)encode(f, lane, vals[k]);
+        store_pair(a, rev, blk, lane, f);
     }
 }
 
@@ -739,8 +748,8 @@ __global__ void __launch_bounds__(kNT) k_ip_down(IpArgs g)
         load_pair(a, rev, blk, lane, f);
         bool r;
         const uint64_t v = decode(f, lane, r);
-        if (encode(f, lane, v + off) || r)
-            store_pair(a, rev, blk, lane, f);
+        (void)encode(f, lane, v + off);
+        store_pair(a, rev, blk, lane, f);
     }
 }
 
@@ -781,15 +790,13 @@ __global__ void __launch_bounds__(kNT) k_ip_tail(IpArgs g)
     const bool rev = a.ctl[1] != 0;
     const int lane = threadIdx.x & 63;
     const uint64_t waves = (uint64_t)gridDim.x * (kNT / 64);
-    const uint64_t pv = a.pivot;
+    const uint64_t pv = a.pivot, lim = a.lo_blk * kB;
     for (uint64_t blk = a.lo_blk + (uint64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6); blk < a.hi_blk;
          blk += waves) {
         Pair<T> f;
         load_pair(a, rev, blk, lane, f);
         bool restored;
         const uint64_t incl = decode(f, lane, restored);
-        if (restored)
-            *ls::phys<T>(a, rev, blk * kB + 2 * (uint64_t)lane + 1) = f.b;
         const uint64_t end = blk == g.nb - 1 ? a.n : (blk + 1) * kB;
         // count the block's predecessors (elements 0..127 are in f, the rest are read)
         uint64_t cnt = (uint64_t)__popcll(__ballot(ls::is_pred(f.a, pv) != rev)) +
@@ -799,29 +806,30 @@ __global__ void __launch_bounds__(kNT) k_ip_tail(IpArgs g)
             cnt += __popcll(__ballot(p));
         }
         uint64_t r = incl - cnt;
-        // the encode area: element 2 lane then 2 lane + 1, in element order
+        // Every target lies in the partitioned prefix [0, lo_blk kB); the bound
+        // is implied by the prefix values and kept as a guard.  With `whole`
+        // each part of the block is written back whole (restored pairs
+        // included), so that its lines are written whole.
         {
+            // the encode area: element 2 lane then 2 lane + 1, in element order
             const bool p0 = ls::is_pred(f.a, pv) != rev, p1 = ls::is_pred(f.b, pv) != rev;
             const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
-            const uint64_t below = lanes_below(m0) + lanes_below(m1);
-            const uint64_t x0 = blk * kB + 2 * (uint64_t)lane;
-            uint64_t rr = r + below;
-            // every target lies in the partitioned prefix [0, lo_blk kB); the
-            // bound is implied by the prefix values and kept as a guard
-            const uint64_t lim = a.lo_blk * kB;
+            uint64_t rr = r + lanes_below(m0) + lanes_below(m1);
             if (p0 && rr < lim) {
                 T *dst = ls::phys<T>(a, rev, rr);
                 const T w = *dst;
                 *dst = f.a;
-                *ls::phys<T>(a, rev, x0) = w;
-                rr++;
+                f.a = w;
             }
+            rr += p0;
             if (p1 && rr < lim) {
                 T *dst = ls::phys<T>(a, rev, rr);
                 const T w = *dst;
                 *dst = f.b;
-                *ls::phys<T>(a, rev, x0 + 1) = w;
+                f.b = w;
             }
+            if (a.whole || p0 || p1 || restored)
+                store_pair(a, rev, blk, lane, f);
             r += __popcll(m0) + __popcll(m1);
         }
         for (uint64_t x0 = blk * kB + 128; x0 < end; x0 += 64) {
@@ -833,12 +841,14 @@ __global__ void __launch_bounds__(kNT) k_ip_tail(IpArgs g)
                 p = ls::is_pred(v, pv) != rev;
             }
             const uint64_t m = __ballot(p);
-            if (p && r + lanes_below(m) < a.lo_blk * kB) {
+            if (p && r + lanes_below(m) < lim) {
                 T *dst = ls::phys<T>(a, rev, r + lanes_below(m));
                 const T w = *dst;
                 *dst = v;
-                *ls::phys<T>(a, rev, x) = w;
+                v = w;
             }
+            if (x < end && (a.whole || p))
+                *ls::phys<T>(a, rev, x) = v;
             r += __popcll(m);
         }
     }
@@ -1075,6 +1085,7 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     a.nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
     a.d_split = d_split;
     a.host = ws->host_dev;
+    a.whole = (uint64_t)n * sizeof(T) > ls::kWholeLineBytes ? 1u : 0u;
     const uint64_t stream_grid = (uint64_t)cus * 8;
     auto grid_for = [&](uint64_t items) -> uint32_t {
         uint64_t g = (items + ls::kNT - 1) / ls::kNT;
@@ -1085,7 +1096,7 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     // mirror passes: one thread per kMirrorU 16-byte vectors of the front half
     auto mirror_grid = [&](uint64_t m) -> uint32_t {
         const uint64_t vec = (m / 2) / (16 / sizeof(T));
-        return grid_for((vec + ls::kMirrorU - 1) / ls::kMirrorU);
+        return grid_for(a.whole ? (vec + ls::kMirrorU - 1) / ls::kMirrorU : vec);
     };
     // 1-2. count with the top preprocessing level, decide the roles
     const uint32_t g1 = mirror_grid(n) < kPartMax ? mirror_grid(n) : kPartMax;
@@ -1136,7 +1147,9 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     for (size_t k = N.size() - 1; k-- > 0;) {
         a.lo_blk = N[k + 1] / ls::kBlock;
         a.hi_blk = (N[k] + ls::kBlock - 1) / ls::kBlock;
-        const uint64_t waves_needed = (a.hi_blk - a.lo_blk + ls::kTailU - 1) / ls::kTailU;
+        // large arrays: kTailU blocks per wavefront; small ones one, for more waves in flight
+        const uint64_t per = a.whole ? ls::kTailU : 1;
+        const uint64_t waves_needed = (a.hi_blk - a.lo_blk + per - 1) / per;
         uint64_t g = (waves_needed + (ls::kNT / 64) - 1) / (ls::kNT / 64);
         if (g > stream_grid)
             g = stream_grid;
@@ -1284,6 +1297,7 @@ int prefix_run(char *base, size_t n, uint64_t pivot, hipStream_t st, uint64_t *d
     a.nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
     a.d_split = d_split;
     a.host = ws->host_dev;
+    a.whole = (uint64_t)n * sizeof(T) > ls::kWholeLineBytes ? 1u : 0u;
     const uint64_t waves_grid = std::min<uint64_t>((nblk + 3) / 4, (uint64_t)cus * 8);
     T *out = reinterpret_cast<T *>(outbuf);
     hipLaunchKernelGGL(ls::k_ps_init, dim3(1), dim3(64), 0, st, a);
