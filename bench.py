@@ -363,14 +363,17 @@ def run_batched(args):
         lat = np.array([ev0.elapsed_time(e) for e in evs])
     splits_p = d_split.cpu().numpy()
     bytes_ = 2 * 8 * total
-    tb = min(te, tg)
+    # the batched call as a user would configure it: the fastest of the measured configurations
+    configs = {"tuned, eager": te, "tuned, graph": tg, "default geometry, eager": t_default}
+    best_cfg = min(configs, key=configs.get)
+    tb = configs[best_cfg]
     tp = min(pt)
     return {"metric": "batched partition GB/s and p99 latency, 20000 uint64 arrays (log-normal, median 2^14)",
             "value": round(bytes_ / tb / 1e9, 1), "unit": "GB/s",
             "batched": {"ms": round(tb * 1e3, 3), "GBps": round(bytes_ / tb / 1e9, 1),
                         "elements_per_s": round(total / tb, 1), "p50_ms": round(tb * 1e3, 3),
                         "p99_ms": round(tb * 1e3, 3), "eager_ms": round(te * 1e3, 3), "graph_ms": round(tg * 1e3, 3),
-                        "launch": "graph" if tg <= te else "eager", "default_geometry_ms": round(t_default * 1e3, 3)},
+                        "configuration": best_cfg, "default_geometry_ms": round(t_default * 1e3, 3)},
             "autotune": {"seconds": round(tune_s, 2),
                          "classes": [{k: c[k] for k in ("max_len", "b", "group_bytes")} for c in tuning["classes"]]},
             "per_array": {"ms": round(tp * 1e3, 3), "GBps": round(bytes_ / tp / 1e9, 1),
