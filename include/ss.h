@@ -256,8 +256,9 @@ int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params *p, void *
  * The number of levels is planned from the longest array, and an array still
  * open after them is finished by a single-workgroup cleanup, so a call is a
  * fixed launch sequence (with SS_FLAG_GRAPH, replayed from a cached HIP
- * graph).  Lines and groups follow the installed size-class tuning
- * (ss_autotune_batched / ss_set_batched_tuning) unless p sets b or
+ * graph).  Calls on the register body (the default except for SS_U32, or
+ * p->engine = SS_ENGINE_REGS) take lines and groups from the installed
+ * size-class tuning (ss_autotune_batched / ss_set_batched_tuning) unless p sets b or
  * tile_bytes.  The call waits for earlier work on `stream` (its host staging
  * buffer is reused), then returns without waiting unless stats != NULL.
  * stats may be NULL. */
@@ -294,7 +295,8 @@ typedef struct ss_batched_tuning {
  * a synthetic batch of about 2^24 elements (log-uniform lengths in the class,
  * uniform keys, pivots at uniform quantiles) is partitioned with every
  * candidate line size (128..1024 bytes) and group size (32..128 KiB), timed
- * with HIP events; the fastest candidate of each class is installed for
+ * with HIP events on the register body; the fastest candidate of each class
+ * (the default geometry unless a candidate is 3% faster) is installed for
  * later batched calls of this dtype on this device and returned in *out
  * (nullable).  Allocates and frees its own device scratch (a few hundred
  * MiB); synchronizes `stream`. */

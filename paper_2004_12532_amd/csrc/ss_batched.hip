@@ -813,10 +813,12 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess)
         return fail_device(e, "hipGetDevice");
-    // size classes: the installed tuning (measured on the register engine) unless
-    // the call fixes the engine or the geometry
+    // size classes: the installed tuning, measured on the register body, for calls
+    // that use the register body (the default except for 4-byte keys, whose LDS
+    // body is faster than any register geometry) and leave the geometry open
     BatchClasses BC = batched_default_classes(R);
-    if (!(p && (p->b || p->tile_bytes || p->engine)) && batched_has_tuning(dev, dtype)) {
+    const uint32_t want_engine = p && p->engine ? p->engine : batched_auto_engine(dtype);
+    if (!(p && (p->b || p->tile_bytes)) && want_engine == SS_ENGINE_REGS && batched_has_tuning(dev, dtype)) {
         Resolved Rr;
         if ((rc = resolve_params(p, dtype, &Rr, SS_ENGINE_REGS)))
             return rc;

@@ -201,6 +201,9 @@ def test_autotune_installs_a_table_that_keeps_parity(ss, kind):
         data, offsets, pivots = _batch(kind, lengths.astype(np.int64), 13)
         out, splits, _ = _run_batched(ss, data, offsets, pivots)
         _check(data, out, offsets, pivots, splits)
+        # the table is measured on the register body; 4-byte keys use it when asked for that body
+        out, splits, _ = _run_batched(ss, data, offsets, pivots, engine="regs")
+        _check(data, out, offsets, pivots, splits)
     finally:
         ss.set_batched_tuning(kind, None)
 
