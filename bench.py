@@ -107,7 +107,7 @@ def _host_cpu() -> str:
 
 def _exit_multi_gpu(gpus):
     if gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1",
+        print("bench.py: the library runs on one GPU (it has no multi-GPU path); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -364,9 +364,9 @@ def run_batched(args):
     splits_p = d_split.cpu().numpy()
     bytes_ = 2 * 8 * total
     # the batched call as a user would configure it: the fastest of the measured configurations
-    configs = {"tuned, eager": te, "tuned, graph": tg, "default geometry, eager": t_default}
-    best_cfg = min(configs, key=configs.get)
-    tb = configs[best_cfg]
+    timings = {"tuned, eager": te, "tuned, graph": tg, "default geometry, eager": t_default}
+    best_cfg = min(timings, key=timings.get)
+    tb = timings[best_cfg]
     tp = min(pt)
     return {"metric": "batched partition GB/s and p99 latency, 20000 uint64 arrays (log-normal, median 2^14)",
             "value": round(bytes_ / tb / 1e9, 1), "unit": "GB/s",
