@@ -302,3 +302,20 @@ def test_implicit_aux_and_async(ss):
     assert oracle.fingerprint(out) == oracle.fingerprint(a0)
     _, st = ss.partition(to_device(a0), p, algo="implicit", stats=True)
     assert st["aux_bytes"] == ss.aux_bytes(n, ss.SS_U64, "implicit")
+
+
+def test_implicit_large_properties(ss):
+    """Above 512 MiB the implicit variant's passes write whole lines: 2^26 + 777 u64
+    keys, distinct and with few distinct values (flipped-element encoding), both
+    majorities, checked by count, side property and multiset."""
+    n = (1 << 26) + 777
+    a0 = workloads.keys_u64(n, 29)
+    few = a0 % np.uint64(5)
+    for keys, q in ((a0, 0.3), (a0, 0.8), (few, 0.5)):
+        p = workloads.pivot_at_quantile_np(keys, q)
+        t = to_device(keys)
+        split = ss.partition(t, p, algo="implicit")
+        out = to_host(t, keys)
+        assert split == oracle.count_less(keys, p)
+        assert oracle.is_partitioned(out, p, split)
+        assert oracle.fingerprint(out) == oracle.fingerprint(keys)
