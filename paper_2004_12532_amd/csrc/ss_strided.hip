@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, cons
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
                           uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint64_t *host, hipStream_t st)
 {
-    constexpr int NT = 1024, BB = 16384;
+    constexpr int NT = 1024, BB = 32768;  // 32 KiB blocks: twice the bytes per serial step of 16 KiB ones
     switch (dtype) {
     case SS_U32:
         hipLaunchKernelGGL((k_cleanup<uint32_t, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count,
