@@ -166,6 +166,41 @@ def test_quicksort_matches_python_sort(kind):
         assert oracle.is_sorted(a)
 
 
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_is_sorted_brute_force_every_short_array(kind):
+    # Every array of length <= 6 over {0..3}: the oracle's verdict equals the
+    # definition (no adjacent pair descends), so an always-true check or one
+    # that skips the first or last pair fails here.
+    for n in range(7):
+        for vals in itertools.product(range(4), repeat=n):
+            want = all(vals[k - 1] <= vals[k] for k in range(1, n))
+            assert oracle.is_sorted(_as(kind, list(vals))) == want, vals
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_is_sorted_detects_planted_inversions(kind):
+    # A sorted array with one descending pair planted at the first pair, the
+    # last pair, a middle pair, and right after a run of equal keys.
+    base = sorted(int(x) for x in np.random.default_rng(11).integers(0, 1 << 30, size=1000))
+    assert oracle.is_sorted(_as(kind, base))
+    for k in (1, len(base) - 1, 500):
+        bad = list(base)
+        bad[k - 1], bad[k] = bad[k] + 1, bad[k - 1]
+        assert not oracle.is_sorted(_as(kind, bad)), k
+    eq = [5] * 40 + [4] + [9] * 10
+    assert not oracle.is_sorted(_as(kind, eq))
+    assert oracle.is_sorted(_as(kind, [5] * 40 + [9] * 10))
+    # the key alone decides: payloads in any order do not matter
+    if kind == "kv":
+        a = _as(kind, [3, 3, 3])
+        a[:, 1] = [9, 1, 5]
+        assert oracle.is_sorted(a)
+    # a u32 key near 2^32 compares as an unsigned value
+    if kind == "u32":
+        assert oracle.is_sorted(_as(kind, [1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF]))
+        assert not oracle.is_sorted(_as(kind, [0xFFFFFFFF, 0x80000000]))
+
+
 def test_quicksort_large_and_duplicates_against_numpy():
     a = workloads.keys_u32(300_000, 9)
     ref = np.sort(a)
