@@ -123,8 +123,7 @@ enum ss_status {
                                   tests. */
 #define SS_FLAG_TIME 2u        /* time the first-level kernel and the whole call with HIP events on
                                   the call's stream; reported in ss_stats (synchronizes). */
-#define SS_FLAG_STREAM 4u      /* register engines: non-temporal (streaming) loads and stores */
-#define SS_FLAG_XCD_ORDER 8u   /* register engines: consecutive groups on the same XCD */
+/* Flag bits 4 and 8 are reserved (unknown flags are rejected with SS_EINVAL). */
 #define SS_FLAG_GRAPH 16u      /* batched calls: issue the level chain as a captured HIP graph, cached per
                                   (stream, buffers, batch shape) and replayed when they recur */
 #define SS_FLAG_EXCHANGE 32u   /* single-array Smoothed Striding, Strided and Hybrid calls: partition
@@ -169,9 +168,6 @@ typedef struct ss_params {
  *                  as whole lines.
  * SS_ENGINE_REGS : the group stays in registers and every element is stored
  *                  straight to its destination (no LDS tile, higher occupancy).
- * SS_ENGINE_REGS2: as SS_ENGINE_REGS with two register buffers: the next
- *                  group's loads are in flight while the current one is
- *                  partitioned (32768- or 65536-byte groups).
  * SS_ENGINE_AUTO : SS_ENGINE_REGS with 131072-byte groups, except for SS_U32
  *                  in ss_partition / ss_partition_ex, which use SS_ENGINE_LDS
  *                  with 32768-byte groups (four 4-byte scattered stores per
@@ -180,11 +176,11 @@ typedef struct ss_params {
  *                  engine with 131072-byte groups, and the LDS engine with
  *                  32768-byte groups for SS_U32; the quicksort's levels use
  *                  the LDS engine with 65536-byte groups for SS_U32.  An
- *                  explicit p->engine / tile_bytes overrides these. */
+ *                  explicit p->engine / tile_bytes overrides these.
+ * Value 3 is reserved (rejected with SS_EINVAL). */
 #define SS_ENGINE_AUTO 0u
 #define SS_ENGINE_LDS 1u
 #define SS_ENGINE_REGS 2u
-#define SS_ENGINE_REGS2 3u
 
 #define SS_MAX_LEVELS 32
 
@@ -259,9 +255,11 @@ int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params *p, void *
  * graph).  Calls on the register body (the default except for SS_U32, or
  * p->engine = SS_ENGINE_REGS) take lines and groups from the installed
  * size-class tuning (ss_autotune_batched / ss_set_batched_tuning) unless p sets b or
- * tile_bytes.  The call waits for earlier work on `stream` (its host staging
- * buffer is reused), then returns without waiting unless stats != NULL.
- * stats may be NULL. */
+ * tile_bytes.  The offsets are staged through one of two pinned host buffers
+ * used alternately; a call waits only until the copy from its buffer, issued
+ * two calls earlier on the stream, has been read, so back-to-back calls queue
+ * on the device without waiting for each other.  It returns without waiting
+ * unless stats != NULL.  stats may be NULL. */
 int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, int dtype,
                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                          void *stream, ss_stats *stats);
@@ -338,8 +336,11 @@ int ss_server_submit(ss_server *s, uint32_t slot, uint64_t start, uint64_t len, 
  * active job will do) and sets the number of partition levels.  At most four
  * ticks are kept in flight (the call waits for the oldest beyond that). */
 int ss_server_tick(ss_server *s, uint64_t max_len);
-/* Wait until at most `in_flight` issued ticks are still running. */
-int ss_server_wait(ss_server *s, uint32_t in_flight);
+/* Wait until at most `in_flight` issued ticks are still running.  *flags
+ * (nullable) receives a copy of the overflow flags kept in mapped host memory:
+ * nonzero once a device list overflowed or a partition was left unfinished
+ * (the bits may be a subset; ss_server_status gives the exact set). */
+int ss_server_wait(ss_server *s, uint32_t in_flight, uint32_t *flags);
 /* 1 if the job in `slot` finished in a completed tick (a partition job's split,
  * relative to its start, in *split if non-NULL), 0 if not, < 0 on error. */
 int ss_server_done(ss_server *s, uint32_t slot, uint64_t *split);

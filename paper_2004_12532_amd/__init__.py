@@ -30,8 +30,7 @@ SS_U32, SS_U64, SS_KV16 = 1, 2, 3
 SMOOTHED, STRIDED, LOWSPACE, HYBRID, MEDIUMSPACE, HIGHSPACE, IMPLICIT = 0, 1, 2, 3, 4, 5, 6
 ALGOS = {"smoothed": SMOOTHED, "strided": STRIDED, "lowspace": LOWSPACE, "hybrid": HYBRID,
          "mediumspace": MEDIUMSPACE, "highspace": HIGHSPACE, "implicit": IMPLICIT}
-FLAG_ONE_LEVEL, FLAG_TIME, FLAG_STREAM, FLAG_XCD_ORDER, FLAG_GRAPH, FLAG_EXCHANGE, FLAG_EXCHANGE_SKEWED, FLAG_STABLE = \
-    1, 2, 4, 8, 16, 32, 64, 128
+FLAG_ONE_LEVEL, FLAG_TIME, FLAG_GRAPH, FLAG_EXCHANGE, FLAG_EXCHANGE_SKEWED, FLAG_STABLE = 1, 2, 16, 32, 64, 128
 MAX_LEVELS = 32
 STATUS = {0: "SS_OK", -1: "SS_EINVAL", -2: "SS_ENOMEM", -3: "SS_EDEVICE", -4: "SS_EUNSUPPORTED",
           -5: "SS_EINCOMPLETE"}
@@ -111,7 +110,7 @@ _lib.ss_server_create.argtypes = [_vp, _sz, _int, _u32, _u32, _vp, ctypes.POINTE
 _lib.ss_server_destroy.argtypes = [_vp]
 _lib.ss_server_submit.argtypes = [_vp, _u32, _u64, _u64, _int, _u64]
 _lib.ss_server_tick.argtypes = [_vp, _u64]
-_lib.ss_server_wait.argtypes = [_vp, _u32]
+_lib.ss_server_wait.argtypes = [_vp, _u32, ctypes.POINTER(_u32)]
 _lib.ss_server_done.argtypes = [_vp, _u32, ctypes.POINTER(_u64)]
 _lib.ss_server_status.argtypes = [_vp, ctypes.POINTER(_u32)]
 _lib.ss_server_job_aux_bytes.argtypes = [_int, _int, _u64]
@@ -175,18 +174,17 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-ENGINES = {"auto": 0, "lds": 1, "regs": 2, "regs2": 3}
+ENGINES = {"auto": 0, "lds": 1, "regs": 2}
 
 
 def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False,
-                engine="auto", stream=False, xcd_order=False, graph=False, exchange="auto") -> Params:
+                engine="auto", graph=False, exchange="auto") -> Params:
     """exchange: "auto" (the library chooses the first level's form from a
     sample), False (stable partition of every group), True (write-minimal
     exchange of every group) or "skewed" (exchange only the groups with few
     misplaced pairs)."""
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
-    flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0) | (FLAG_STREAM if stream else 0) \
-        | (FLAG_XCD_ORDER if xcd_order else 0) | (FLAG_GRAPH if graph else 0) \
+    flags = (FLAG_ONE_LEVEL if one_level else 0) | (FLAG_TIME if time else 0) | (FLAG_GRAPH if graph else 0) \
         | {"auto": 0, "skewed": FLAG_EXCHANGE_SKEWED, True: FLAG_EXCHANGE, False: FLAG_STABLE}[exchange]
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
     return Params(a, b, tile_bytes, max_levels, seed, flags, e)
@@ -332,8 +330,13 @@ class ServerEngine:
     def tick(self, max_len: int) -> None:
         _check(_lib.ss_server_tick(self._h, max_len), "ss_server_tick")
 
-    def wait(self, in_flight: int = 0) -> None:
-        _check(_lib.ss_server_wait(self._h, in_flight), "ss_server_wait")
+    def wait(self, in_flight: int = 0) -> int:
+        """Wait until at most `in_flight` ticks run; returns the overflow flags
+        mirrored in host memory (nonzero: a device list overflowed or a
+        partition was left unfinished)."""
+        f = _u32(0)
+        _check(_lib.ss_server_wait(self._h, in_flight, ctypes.byref(f)), "ss_server_wait")
+        return int(f.value)
 
     def done(self, slot: int):
         """(finished, split) for the job in slot; split only for partition jobs."""

@@ -162,26 +162,18 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
         q = *p;
     if (q.algo < SS_SMOOTHED || q.algo > SS_IMPLICIT)
         return fail_msg(SS_EINVAL, "unknown algo");
-    if (q.flags &
-        ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | SS_FLAG_GRAPH | kExchangeFlags |
-          SS_FLAG_STABLE))
+    if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_GRAPH | kExchangeFlags | SS_FLAG_STABLE))
         return fail_msg(SS_EINVAL, "unknown flags");
-    if (q.engine > SS_ENGINE_REGS2)
+    if (q.engine > SS_ENGINE_REGS)
         return fail_msg(SS_EINVAL, "unknown engine");
     uint32_t engine = q.engine ? q.engine : auto_engine;
-    if (!q.engine && engine == SS_ENGINE_LDS &&
-        (q.tile_bytes == 131072u || (q.flags & (SS_FLAG_STREAM | SS_FLAG_XCD_ORDER | kExchangeFlags))))
+    if (!q.engine && engine == SS_ENGINE_LDS && (q.tile_bytes == 131072u || (q.flags & kExchangeFlags)))
         engine = SS_ENGINE_REGS;  // options only the register engine has
-    const uint32_t tile = q.tile_bytes ? q.tile_bytes
-                         : engine == SS_ENGINE_LDS  ? 32768u
-                         : engine == SS_ENGINE_REGS2 ? 65536u
-                                                     : kDefaultRegsTile;
+    const uint32_t tile = q.tile_bytes ? q.tile_bytes : engine == SS_ENGINE_LDS ? 32768u : kDefaultRegsTile;
     if (tile != 32768u && tile != 65536u && !(tile == 131072u && engine == SS_ENGINE_REGS))
-        return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (single-buffer register engine) 131072");
-    if ((q.flags & SS_FLAG_STREAM) && engine == SS_ENGINE_LDS)
-        return fail_msg(SS_EINVAL, "streaming hints apply to the register engines");
+        return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (register engine) 131072");
     if ((q.flags & kExchangeFlags) && engine == SS_ENGINE_LDS)
-        return fail_msg(SS_EINVAL, "the write-minimal exchange applies to the register engines");
+        return fail_msg(SS_EINVAL, "the write-minimal exchange applies to the register engine");
     const uint32_t b = q.b ? q.b : kDefaultLineBytes / w;
     const uint64_t line = (uint64_t)b * w;
     if (b == 0 || (b & (b - 1)) || line < 64 || line > 4096 || line > tile)
@@ -202,34 +194,29 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     // The automatic first-level choice needs the default geometry and the
     // register engine, and pays only for 8- and 16-byte elements.
     r->auto_xch = !q.engine && !q.tile_bytes && !q.b && w >= 8 && engine == SS_ENGINE_REGS &&
-                  !(q.flags & (kExchangeFlags | SS_FLAG_STABLE | SS_FLAG_STREAM | SS_FLAG_XCD_ORDER)) &&
+                  !(q.flags & (kExchangeFlags | SS_FLAG_STABLE)) &&
                   (q.algo == SS_SMOOTHED || q.algo == SS_STRIDED || q.algo == SS_HYBRID);
     return SS_OK;
 }
 
-#define SS_LDS_VARIANT(D, T, NT, TB) \
-    {D, SS_ENGINE_LDS, TB, false, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr}
-#define SS_RS_VARIANT(D, T, E, NT, NV, NTMP, DB)                                                              \
-    {D, E, NT * NV * 16, NTMP, NT, &launch_level_rs<T, NT, NV, NTMP, DB>, &level_rs_fn<T, NT, NV, NTMP, DB>, \
-     &launch_level_xch<T, NT, NV, NTMP, DB>, &level_xch_fn<T, NT, NV, NTMP, DB>}
-#define SS_RS_ALL(E, NT, NV, NTMP, DB)                                                     \
-    SS_RS_VARIANT(SS_U32, uint32_t, E, NT, NV, NTMP, DB), SS_RS_VARIANT(SS_U64, uint64_t, E, NT, NV, NTMP, DB), \
-        SS_RS_VARIANT(SS_KV16, KV, E, NT, NV, NTMP, DB)
+#define SS_LDS_VARIANT(D, T, NT, TB) {D, SS_ENGINE_LDS, TB, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr}
+#define SS_RS_VARIANT(D, T, NT, NV)                                                                  \
+    {D, SS_ENGINE_REGS, NT * NV * 16, NT, &launch_level_rs<T, NT, NV>, &level_rs_fn<T, NT, NV>, \
+     &launch_level_xch<T, NT, NV>, &level_xch_fn<T, NT, NV>}
+#define SS_RS_ALL(NT, NV) \
+    SS_RS_VARIANT(SS_U32, uint32_t, NT, NV), SS_RS_VARIANT(SS_U64, uint64_t, NT, NV), SS_RS_VARIANT(SS_KV16, KV, NT, NV)
 
-const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile, bool stream)
+const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile)
 {
     static const Variant v[] = {
         SS_LDS_VARIANT(SS_U32, uint32_t, 256, 65536), SS_LDS_VARIANT(SS_U64, uint64_t, 256, 65536),
         SS_LDS_VARIANT(SS_KV16, KV, 256, 65536),      SS_LDS_VARIANT(SS_U32, uint32_t, 256, 32768),
         SS_LDS_VARIANT(SS_U64, uint64_t, 256, 32768), SS_LDS_VARIANT(SS_KV16, KV, 256, 32768),
-        SS_RS_ALL(SS_ENGINE_REGS, 256, 8, false, false),  SS_RS_ALL(SS_ENGINE_REGS, 512, 8, false, false),
-        SS_RS_ALL(SS_ENGINE_REGS, 512, 16, false, false), SS_RS_ALL(SS_ENGINE_REGS, 256, 8, true, false),
-        SS_RS_ALL(SS_ENGINE_REGS, 512, 8, true, false),   SS_RS_ALL(SS_ENGINE_REGS, 512, 16, true, false),
-        SS_RS_ALL(SS_ENGINE_REGS2, 512, 4, false, true),  SS_RS_ALL(SS_ENGINE_REGS2, 512, 8, false, true),
-        SS_RS_ALL(SS_ENGINE_REGS2, 512, 4, true, true),   SS_RS_ALL(SS_ENGINE_REGS2, 512, 8, true, true),
+        SS_RS_ALL(256, 8),                            SS_RS_ALL(512, 8),
+        SS_RS_ALL(512, 16),
     };
     for (const Variant &x : v)
-        if (x.dtype == dtype && x.engine == engine && x.tile == tile && x.stream == stream)
+        if (x.dtype == dtype && x.engine == engine && x.tile == tile)
             return &x;
     return nullptr;
 }
@@ -276,7 +263,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     rc = get_workspace(dev, st, &ws);
     if (rc)
         return rc;
-    const Variant *V = pick_variant(dtype, R.engine, R.tile, (R.flags & SS_FLAG_STREAM) != 0);
+    const Variant *V = pick_variant(dtype, R.engine, R.tile);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
     // The exchange tables (16-bit slot numbers) are dynamic LDS.
@@ -294,8 +281,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     // Levels from the third on work on regions a few hundred times smaller
     // than the array; there a group is latency-bound, so they use 32 KiB
     // groups of 128-byte lines (more, shorter groups per level).
-    const Variant *Vt = pick_variant(dtype, R.engine == SS_ENGINE_LDS ? SS_ENGINE_LDS : SS_ENGINE_REGS, 32768u,
-                                     R.engine != SS_ENGINE_LDS && (R.flags & SS_FLAG_STREAM) != 0);
+    const Variant *Vt = pick_variant(dtype, R.engine, 32768u);
     if (!Vt)
         return fail_msg(SS_EUNSUPPORTED, "no tail kernel variant");
     int occ_t = 0;
@@ -321,7 +307,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const Variant *Vx = nullptr;
     uint32_t Px = 0;
     if (autox) {
-        Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u, false);
+        Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u);
         if (!Vx || !Vx->fn_x)
             return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
         int occ_x = 0;
@@ -350,7 +336,6 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         a.log2b = R.log2b;
         a.s_max = R.s_max;
         a.strided = strided ? 1u : 0u;
-        a.order = (R.flags & SS_FLAG_XCD_ORDER) ? 1u : 0u;
         a.xch_shift = (R.flags & SS_FLAG_EXCHANGE_SKEWED) ? kSkewShift : 0u;
         uint32_t prev_count = 0;
         const uint64_t *prev = nullptr;

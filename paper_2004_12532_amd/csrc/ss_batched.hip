@@ -431,11 +431,18 @@ __global__ void __launch_bounds__(256) k_bfinish(BatchState B, uint64_t *d_split
 
 namespace {
 
+// Per (device, stream): the device state of a batched call, and two pinned
+// host staging buffers for the starts and lengths, used alternately.  A call
+// waits only for the copy issued from its buffer two calls earlier (its
+// event), never for the whole stream, so back-to-back calls queue on the
+// device without a host stall.
 struct BatchWork {
     char *dev = nullptr;
     size_t dev_bytes = 0;
-    uint64_t *host = nullptr;  // pinned staging for start/len
+    uint64_t *host[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
     size_t host_words = 0;
+    uint32_t next = 0;
 };
 std::mutex g_b_mu;
 std::map<std::pair<int, void *>, BatchWork> g_b;
@@ -615,7 +622,8 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
     return SS_OK;
 }
 
-int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage)
+int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage,
+                  hipEvent_t *stage_copied)
 {
     std::lock_guard<std::mutex> lk(g_b_mu);
     BatchWork &w = g_b[std::make_pair(dev, stream)];
@@ -626,7 +634,7 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
     if (w.dev_bytes < bytes) {
         if (w.dev) {
             batched_graphs_forget(w.dev);
-            (void)hipFree(w.dev);
+            (void)hipFree(w.dev);  // synchronizes the device: no earlier call still uses it
         }
         w.dev = nullptr;
         w.dev_bytes = 0;
@@ -636,18 +644,35 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
         }
         w.dev_bytes = bytes;
     }
+    for (auto &ev : w.copied)
+        if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return fail_device(e, "hipEventCreate");
     const size_t hwords = 2 * (size_t)num + 2;
     if (w.host_words < hwords) {
-        if (w.host)
-            (void)hipHostFree(w.host);
-        w.host = nullptr;
-        w.host_words = 0;
-        if ((e = hipHostMalloc((void **)&w.host, hwords * sizeof(uint64_t), hipHostMallocDefault)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail_msg(SS_ENOMEM, std::string("batched staging hipHostMalloc: ") + hipGetErrorString(e));
+        for (int k = 0; k < 2; k++) {
+            if (w.host[k]) {
+                if ((e = hipEventSynchronize(w.copied[k])) != hipSuccess)  // its last copy has been read
+                    return fail_device(e, "hipEventSynchronize");
+                (void)hipHostFree(w.host[k]);
+            }
+            w.host[k] = nullptr;
         }
+        w.host_words = 0;
+        for (int k = 0; k < 2; k++)
+            if ((e = hipHostMalloc((void **)&w.host[k], hwords * sizeof(uint64_t), hipHostMallocDefault)) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                return fail_msg(SS_ENOMEM, std::string("batched staging hipHostMalloc: ") + hipGetErrorString(e));
+            }
         w.host_words = hwords;
     }
+    const uint32_t k = w.next;
+    w.next ^= 1u;
+    // the copy issued from this buffer two calls ago must have been read
+    if ((e = hipEventSynchronize(w.copied[k])) != hipSuccess)
+        return fail_device(e, "hipEventSynchronize");
+    *host_stage = w.host[k];
+    *stage_copied = w.copied[k];
     uint64_t *p = reinterpret_cast<uint64_t *>(w.dev);
     B->ctl = p;
     p += 8;
@@ -672,7 +697,6 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
     B->cls = reinterpret_cast<uint8_t *>(p);
     B->count = nullptr;
     B->num = num;
-    *host_stage = w.host;
     return SS_OK;
 }
 
@@ -699,13 +723,14 @@ struct GraphKey {
     void *stream;
     const void *base, *pivots, *splits, *state;
     int dtype;
-    uint32_t num, levels, tile, log2b;
-    uint64_t items_cap, seed;
+    uint32_t num, levels, tile, engine, flags;
+    uint64_t items_cap, seed, classes;  // classes: hash of the size-class table baked into the arguments
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(dev, stream, base, pivots, splits, state, dtype, num, levels, tile, log2b, items_cap, seed) <
-               std::tie(o.dev, o.stream, o.base, o.pivots, o.splits, o.state, o.dtype, o.num, o.levels, o.tile,
-                        o.log2b, o.items_cap, o.seed);
+        return std::tie(dev, stream, base, pivots, splits, state, dtype, num, levels, tile, engine, flags, items_cap,
+                        seed, classes) < std::tie(o.dev, o.stream, o.base, o.pivots, o.splits, o.state, o.dtype,
+                                                  o.num, o.levels, o.tile, o.engine, o.flags, o.items_cap, o.seed,
+                                                  o.classes);
     }
 };
 
@@ -727,15 +752,14 @@ int batched_graph(int dev, char *base, int dtype, const Resolved &R, const Batch
                   uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches)
 {
     std::lock_guard<std::mutex> lk(g_gr_mu);
-    GraphKey key{dev, (void *)st, base, B.pivot, d_splits, B.ctl, dtype, B.num, levels, R.tile, 0u,
-                 items_cap, R.seed};
-    // the class table is baked into the kernel arguments: fold it into the key
+    // The engine picks the kernel bodies and the class table is baked into the
+    // kernel arguments: both are part of the key (the table as an FNV-1a hash).
     uint64_t h = 1469598103934665603ull;
     const unsigned char *cb = reinterpret_cast<const unsigned char *>(&BC);
     for (size_t j = 0; j < sizeof(BC); j++)
         h = (h ^ cb[j]) * 1099511628211ull;
-    key.log2b = (uint32_t)(h ^ (h >> 32));
-    key.seed ^= h;
+    GraphKey key{dev, (void *)st, base, B.pivot, d_splits, B.ctl, dtype, B.num, levels, R.tile, R.engine,
+                 R.flags & ~(uint32_t)SS_FLAG_TIME, items_cap, R.seed, h};
     hipError_t e;
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -806,8 +830,6 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         return rc;
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "batched partition uses Smoothed Striding");
-    if (R.engine == SS_ENGINE_REGS2)
-        return fail_msg(SS_EUNSUPPORTED, "batched partition uses the single-buffer register or the LDS engine");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int dev = 0;
@@ -847,15 +869,14 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         levels = R.levels;
     BatchState B;
     uint64_t *stage = nullptr;
-    if ((rc = batched_state(dev, stream, (uint32_t)num, items_cap, &B, &stage)))
+    hipEvent_t stage_copied = nullptr;
+    if ((rc = batched_state(dev, stream, (uint32_t)num, items_cap, &B, &stage, &stage_copied)))
         return rc;
     B.pivot = d_pivots;
-    // the previous call on this stream may still read the staging buffer
-    if ((e = hipStreamSynchronize(st)) != hipSuccess)
-        return fail_device(e, "hipStreamSynchronize");
     std::memcpy(stage, starts, num * sizeof(uint64_t));
     std::memcpy(stage + num, lens, num * sizeof(uint64_t));
-    if ((e = hipMemcpyAsync(B.start, stage, 2 * num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess)
+    if ((e = hipMemcpyAsync(B.start, stage, 2 * num * sizeof(uint64_t), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipEventRecord(stage_copied, st)) != hipSuccess)
         return fail_device(e, "hipMemcpyAsync");
     RunOut ro;
     std::memset(&ro, 0, sizeof(ro));
@@ -1064,17 +1085,15 @@ static int autotune(int dtype, hipStream_t st, ss_batched_tuning *out)
                 for (int rep = 0; rep < 3 && rc == SS_OK; rep++) {
                     BatchState B;
                     uint64_t *stage = nullptr;
-                    if ((rc = batched_state(dev, st, num, items_cap, &B, &stage)))
+                    hipEvent_t stage_copied = nullptr;
+                    if ((rc = batched_state(dev, st, num, items_cap, &B, &stage, &stage_copied)))
                         break;
                     B.pivot = d_piv;
-                    if ((e = hipStreamSynchronize(st)) != hipSuccess) {
-                        rc = fail_device(e, "hipStreamSynchronize");
-                        break;
-                    }
                     std::memcpy(stage, starts.data(), num * sizeof(uint64_t));
                     std::memcpy(stage + num, lens.data(), num * sizeof(uint64_t));
                     if ((e = hipMemcpyAsync(B.start, stage, 2 * (size_t)num * sizeof(uint64_t),
                                             hipMemcpyHostToDevice, st)) != hipSuccess ||
+                        (e = hipEventRecord(stage_copied, st)) != hipSuccess ||
                         (e = hipMemcpyAsync(data, pristine, (size_t)total * w, hipMemcpyDeviceToDevice, st)) !=
                             hipSuccess) {
                         rc = fail_device(e, "hipMemcpyAsync");

@@ -84,7 +84,6 @@ struct LevelArgs {
     uint32_t log2b;         // log2 of elements per line
     uint32_t s_max;         // lines-per-group bound
     uint32_t strided;       // 1: every offset is 0 (the Strided Algorithm)
-    uint32_t order;         // 1: XCD-grouped assignment of groups to workgroups
     uint32_t xch_shift;     // exchange form: a group whose misplaced pairs m satisfy m << xch_shift > slots
                             // is stored stably instead (0: every group by exchange)
     uint32_t gate_want;     // first level: run only if *gate == gate_want, else only neutral partials

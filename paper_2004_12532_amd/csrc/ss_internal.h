@@ -70,7 +70,6 @@ struct Variant {
     int dtype;
     uint32_t engine;
     uint32_t tile;
-    bool stream;
     int nt;
     hipError_t (*launch)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
     const void *(*fn)(bool first);
@@ -83,15 +82,15 @@ template <typename T, int NT, int TB>
 hipError_t launch_level(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int TB>
 const void *level_fn(bool first);
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 const void *level_rs_fn(bool first);
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 const void *level_xch_fn(bool first);
-const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile, bool stream);
+const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile);
 hipError_t launch_xch_prepare(int dtype, const char *base, uint64_t n, uint64_t pivot, uint64_t *result, bool force,
                               hipStream_t st);
 hipError_t launch_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl, uint64_t *result,
@@ -140,7 +139,8 @@ struct BatchState {
     const uint32_t *count;  // device word holding the number of arrays (nullable: then num)
     uint32_t num;      // number of arrays, or the capacity when count is set (sizes the grids)
 };
-int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage);
+int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage,
+                  hipEvent_t *stage_copied);
 uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems);
 uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems);
 int batched_graph(int dev, char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B,

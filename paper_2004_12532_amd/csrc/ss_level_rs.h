@@ -41,10 +41,10 @@
 
 namespace ss {
 
-template <typename T, int NT, int NV, bool FIRST, bool NTMP, bool DB, bool XCH>
+template <typename T, int NT, int NV, bool FIRST, bool XCH>
 __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 {
-    using Ctx = LevelCtx<T, NT, NV, NTMP>;
+    using Ctx = LevelCtx<T, NT, NV>;
     constexpr int W = Ctx::W;
     constexpr int NW = Ctx::NW;
     constexpr int MAXS = Ctx::NVEC * 16 / 64;  // lines of at least 64 bytes
@@ -143,48 +143,21 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             return f ? x.template partition<true>(buf, i, m) : x.template partition<false>(buf, i, m);
     };
 
+    // One register buffer: the next group's loads are issued right after this
+    // group's stores, before the barrier that lets the counts be rewritten.
     const uint32_t step = gridDim.x;
-    // Workgroups are dispatched round-robin over the 8 XCDs; with order = 1 the
-    // groups a workgroup starts from are renumbered so that consecutive groups
-    // (adjacent lines of every chunk) run on the same XCD.
-    const uint32_t first = (a.order && (step & 7) == 0) ? (bid & 7) * (step >> 3) + (bid >> 3) : bid;
-    if (!DB) {
-        // One register buffer: the next group's loads are issued after this group's stores.
-        v4u buf[NV];
-        Mask m;
-        uint32_t i = first;
-        bool fast = false;
+    v4u buf[NV];
+    Mask m;
+    uint32_t i = bid;
+    bool fast = false;
+    if (i < G.g)
+        fast = load_any(buf, i, m);
+    while (i < G.g) {
+        fold(part_any(buf, i, fast, m), i);
+        i += step;
         if (i < G.g)
             fast = load_any(buf, i, m);
-        while (i < G.g) {
-            fold(part_any(buf, i, fast, m), i);
-            i += step;
-            if (i < G.g)
-                fast = load_any(buf, i, m);
-            __syncthreads();  // the counts are rewritten by the next group
-        }
-    } else {
-        // Two register buffers: the next group's loads are issued before this group is partitioned.
-        v4u ba[NV], bb[NV];
-        Mask ma, mb;
-        uint32_t i = first;
-        bool fa = false, fb = false;
-        if (i < G.g)
-            fa = load_any(ba, i, ma);
-        while (i < G.g) {
-            if (i + step < G.g)
-                fb = load_any(bb, i + step, mb);
-            fold(part_any(ba, i, fa, ma), i);
-            __syncthreads();
-            i += step;
-            if (i >= G.g)
-                break;
-            if (i + step < G.g)
-                fa = load_any(ba, i + step, ma);
-            fold(part_any(bb, i, fb, mb), i);
-            __syncthreads();
-            i += step;
-        }
+        __syncthreads();  // the counts are rewritten by the next group
     }
     if (tid == 0) {
         a.out[2 * bid] = vmin;
@@ -194,38 +167,34 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     }
 }
 
-template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
+template <typename T, int NT, int NV, bool XCH>
 const void *level_rs_fn_t(bool first)
 {
-    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, NTMP, DB, XCH>)
-                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, NTMP, DB, XCH>);
+    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, XCH>)
+                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, XCH>);
 }
 
 // Launch of the stable form (XCH = false) or the exchange form (XCH = true),
 // whose table of slot numbers is dynamic LDS.
-template <typename T, int NT, int NV, bool NTMP, bool DB, bool XCH>
+template <typename T, int NT, int NV, bool XCH>
 hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
 {
-    const size_t shmem = XCH ? LevelCtx<T, NT, NV, NTMP>::XCH_BYTES : 0;
+    const size_t shmem = XCH ? LevelCtx<T, NT, NV>::XCH_BYTES : 0;
     if (shmem > 32768) {
-        const hipError_t e = hipFuncSetAttribute(level_rs_fn_t<T, NT, NV, NTMP, DB, XCH>(first),
+        const hipError_t e = hipFuncSetAttribute(level_rs_fn_t<T, NT, NV, XCH>(first),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess)
             return e;
     }
     if (first)
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, XCH>), dim3(grid), dim3(NT), shmem, st, a);
     else
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, NTMP, DB, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, XCH>), dim3(grid), dim3(NT), shmem, st, a);
     return hipGetLastError();
 }
 
-// Every register-engine variant the host selects from: single buffer with
-// groups of 32, 64 and 128 KiB, double buffer with 32 and 64 KiB, each with
-// and without streaming hints.  X(T, NT, NV, NTMP, DB) is applied to each.
-#define SS_RS_VARIANTS(X, T)                                                                        \
-    X(T, 256, 8, false, false) X(T, 512, 8, false, false) X(T, 512, 16, false, false)               \
-    X(T, 256, 8, true, false) X(T, 512, 8, true, false) X(T, 512, 16, true, false)                  \
-    X(T, 512, 4, false, true) X(T, 512, 8, false, true) X(T, 512, 4, true, true) X(T, 512, 8, true, true)
+// The register-engine group shapes the host selects from: groups of 32, 64 and
+// 128 KiB (threads x 16-byte vectors per thread).  X(T, NT, NV) is applied to each.
+#define SS_RS_VARIANTS(X, T) X(T, 256, 8) X(T, 512, 8) X(T, 512, 16)
 
 }  // namespace ss

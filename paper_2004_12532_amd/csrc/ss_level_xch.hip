@@ -7,21 +7,21 @@
 
 namespace ss {
 
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
 {
-    return launch_level_rs_t<T, NT, NV, NTMP, DB, true>(first, grid, a, st);
+    return launch_level_rs_t<T, NT, NV, true>(first, grid, a, st);
 }
 
-template <typename T, int NT, int NV, bool NTMP, bool DB>
+template <typename T, int NT, int NV>
 const void *level_xch_fn(bool first)
 {
-    return level_rs_fn_t<T, NT, NV, NTMP, DB, true>(first);
+    return level_rs_fn_t<T, NT, NV, true>(first);
 }
 
-#define SS_INSTANTIATE_XCH(T, NT, NV, NTMP, DB)                                                              \
-    template hipError_t launch_level_xch<T, NT, NV, NTMP, DB>(bool, uint32_t, const LevelArgs &, hipStream_t); \
-    template const void *level_xch_fn<T, NT, NV, NTMP, DB>(bool);
+#define SS_INSTANTIATE_XCH(T, NT, NV)                                                              \
+    template hipError_t launch_level_xch<T, NT, NV>(bool, uint32_t, const LevelArgs &, hipStream_t); \
+    template const void *level_xch_fn<T, NT, NV>(bool);
 
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint32_t)
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint64_t)

@@ -12,33 +12,7 @@
 
 namespace ss {
 
-template <bool NTMP>
-__device__ __forceinline__ v4u load_vec(const char *p)
-{
-    if (NTMP)
-        return __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
-    return *reinterpret_cast<const v4u *>(p);
-}
-
-template <bool NTMP, typename T>
-__device__ __forceinline__ void store_elem(const v4u &v, int e, char *p)
-{
-    if (NTMP) {
-        if constexpr (sizeof(T) == 4) {
-            __builtin_nontemporal_store(e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w, reinterpret_cast<uint32_t *>(p));
-        } else if constexpr (sizeof(T) == 8) {
-            typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-            const v2u x = e == 0 ? v2u{v.x, v.y} : v2u{v.z, v.w};
-            __builtin_nontemporal_store(x, reinterpret_cast<v2u *>(p));
-        } else {
-            __builtin_nontemporal_store(v, reinterpret_cast<v4u *>(p));
-        }
-    } else {
-        Elem<T>::store1(v, e, p);
-    }
-}
-
-template <typename T, int NT, int NV, bool NTMP = false>
+template <typename T, int NT, int NV>
 struct LevelCtx {
     static constexpr int W = sizeof(T);
     static constexpr int LOG2W = W == 4 ? 2 : W == 8 ? 3 : 4;
@@ -96,7 +70,7 @@ struct LevelCtx {
         for (int r = 0; r < NV; r++) {
             const uint32_t q = r * NT + tid;
             if (FAST) {
-                buf[r] = load_vec<NTMP>(elem_ptr(vec_start(q, i)));
+                buf[r] = *reinterpret_cast<const v4u *>(elem_ptr(vec_start(q, i)));
             } else {
                 buf[r] = v4u{0u, 0u, 0u, 0u};
                 if (q < nvec) {
@@ -221,7 +195,7 @@ struct LevelCtx {
     {
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
             if (FAST || ((m.real >> (r * V + e)) & 1))
-                store_elem<NTMP, T>(buf[r], e, slot_ptr(p ? rp : c + slot - rp, i));
+                Elem<T>::store1(buf[r], e, slot_ptr(p ? rp : c + slot - rp, i));
         });
     }
 
@@ -301,7 +275,7 @@ struct LevelCtx {
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
             if (p && slot >= c) {
                 const uint32_t k = c - rp - 1;
-                store_elem<NTMP, T>(buf[r], e, slot_ptr(xt[k], i));
+                Elem<T>::store1(buf[r], e, slot_ptr(xt[k], i));
                 xt[k] = (uint16_t)slot;
             }
         });
@@ -309,7 +283,7 @@ struct LevelCtx {
         // (3) each misplaced successor stores itself at its partner's slot
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
             if (!p && slot < c)
-                store_elem<NTMP, T>(buf[r], e, slot_ptr(xt[slot - rp], i));
+                Elem<T>::store1(buf[r], e, slot_ptr(xt[slot - rp], i));
         });
         return c;
     }

@@ -514,8 +514,6 @@ extern "C" int ss_quicksort_ex(void *d_ptr, size_t n, int dtype, const ss_params
     }
     if (R.algo != SS_SMOOTHED)
         return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the batched Smoothed Striding partition");
-    if (R.engine == SS_ENGINE_REGS2)
-        return fail_msg(SS_EUNSUPPORTED, "quicksort levels use the single-buffer register or the LDS engine");
     if ((rc = check_lines(n, R)))
         return rc;
     hipStream_t st = (hipStream_t)stream;

@@ -51,9 +51,21 @@ struct SrvDev {
     uint32_t *outstanding;
     uint32_t *h_done;     // mapped host memory
     uint64_t *h_split;    // mapped host memory
+    uint32_t *h_flags;    // mapped host memory: a copy of the overflow flags (nonzero once any is set)
     uint32_t cap_segs, cap_leaves, max_jobs;
     uint64_t leaf_cap;
 };
+
+// Raise overflow flag bits on the device and mirror them into mapped host
+// memory, so the host sees a failure at its next wait without synchronizing.
+// Concurrent raisers may leave the mirror with a subset of the bits, never
+// with none; ss_server_status reads the exact set.
+__device__ __forceinline__ void srv_flag(const SrvDev &D, uint32_t bits)
+{
+    const uint32_t old = atomicOr(&D.count[3], bits);
+    *reinterpret_cast<volatile uint32_t *>(D.h_flags) = old | bits;
+    __threadfence_system();
+}
 
 __device__ __forceinline__ void srv_finish(const SrvDev &D, uint32_t slot)
 {
@@ -76,7 +88,7 @@ __global__ void __launch_bounds__(256) k_ssubmit(SrvDev D, const SrvSub *sub, ui
     const uint32_t k = atomicAdd(&D.count[cur], 1u);
     if (k >= D.cap_segs) {  // admission keeps this from happening; keep the count within capacity
         atomicSub(&D.count[cur], 1u);
-        atomicOr(&D.count[3], 1u);
+        srv_flag(D, 1u);
         return;
     }
     D.start[cur][k] = x.start;
@@ -124,7 +136,7 @@ __device__ __forceinline__ uint32_t srv_emit(const SrvDev &D, uint32_t nxt, uint
         const uint32_t i = atomicAdd(&D.count[nxt], 1u);
         if (i >= D.cap_segs) {
             atomicSub(&D.count[nxt], 1u);
-            atomicOr(&D.count[3], 1u);
+            srv_flag(D, 1u);
             return 0;
         }
         D.start[nxt][i] = s;
@@ -137,7 +149,7 @@ __device__ __forceinline__ uint32_t srv_emit(const SrvDev &D, uint32_t nxt, uint
         const uint32_t i = atomicAdd(&D.count[2], 1u);
         if (i >= D.cap_leaves) {
             atomicSub(&D.count[2], 1u);
-            atomicOr(&D.count[3], 1u);
+            srv_flag(D, 1u);
             return 0;
         }
         D.leaf_start[i] = s;
@@ -156,7 +168,7 @@ __global__ void __launch_bounds__(256) k_schild(SrvDev D, uint32_t cur, const ui
     const uint32_t slot = D.job[cur][k], nxt = cur ^ 1u;
     const uint64_t s = D.start[cur][k], l = D.len[cur][k], rel = split[k] - s;
     if (split[k] < s || rel > l) {  // an unfinished partition (the batched chain ends with a cleanup)
-        atomicOr(&D.count[3], 2u);
+        srv_flag(D, 2u);
         return;
     }
     if (D.kind[slot] == 0) {
@@ -289,7 +301,7 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
         delete s;
         return fail_msg(SS_ENOMEM, std::string("server state: ") + hipGetErrorString(e));
     }
-    const size_t hbytes = (size_t)max_jobs * (sizeof(uint32_t) + sizeof(uint64_t)) + 64;
+    const size_t hbytes = (size_t)max_jobs * (sizeof(uint32_t) + sizeof(uint64_t)) + 128;
     if ((e = hipHostMalloc((void **)&s->hmem, hbytes, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess) {
         (void)hipGetLastError();
         server_free(s);
@@ -325,6 +337,7 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
     D.outstanding = reinterpret_cast<uint32_t *>(take(max_jobs / 2 + 1));
     D.h_done = hdev;
     D.h_split = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(hdev) + ((size_t)max_jobs * 4 + 63) / 64 * 64);
+    D.h_flags = reinterpret_cast<uint32_t *>(D.h_split + max_jobs);
     D.cap_segs = (uint32_t)cap_segs;
     D.cap_leaves = (uint32_t)cap_leaves;
     D.max_jobs = max_jobs;
@@ -482,9 +495,10 @@ extern "C" int ss_server_tick(ss_server *h, uint64_t max_len)
     return SS_OK;
 }
 
-// Wait until at most `in_flight` issued ticks are still running; returns the
-// overflow flags (nonzero means a capacity was exceeded: a bug in admission).
-extern "C" int ss_server_wait(ss_server *h, uint32_t in_flight)
+// Wait until at most `in_flight` issued ticks are still running; *flags
+// (nullable) receives the mirrored overflow flags (nonzero: a capacity was
+// exceeded, which admission is meant to prevent).
+extern "C" int ss_server_wait(ss_server *h, uint32_t in_flight, uint32_t *flags)
 {
     if (!h)
         return fail_msg(SS_EINVAL, "null server");
@@ -494,6 +508,10 @@ extern "C" int ss_server_wait(ss_server *h, uint32_t in_flight)
         if ((e = hipEventSynchronize(s->tick_ev[s->ticks_done & 3])) != hipSuccess)
             return fail_device(e, "hipEventSynchronize");
         s->ticks_done++;
+    }
+    if (flags) {
+        const size_t off = ((size_t)s->D.max_jobs * 4 + 63) / 64 * 64 + (size_t)s->D.max_jobs * 8;
+        *flags = *reinterpret_cast<volatile uint32_t *>(reinterpret_cast<char *>(s->hmem) + off);
     }
     return SS_OK;
 }

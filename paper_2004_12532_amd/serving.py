@@ -219,7 +219,8 @@ class Server:
             self.ticks += 1
             self.max_batch = max(self.max_batch, len(active))
             # look at the results of the previous tick while this one runs
-            self.engine.wait(1)
+            if self.engine.wait(1):
+                raise RuntimeError("serving engine capacity exceeded (flags %d)" % self.engine.status())
             now = time.perf_counter() - t0
             still = []
             for job in active:

@@ -82,16 +82,25 @@ def test_batched_unaligned_starts_and_tiles(ss):
 
 
 def test_batched_config_shape_properties(ss):
-    """The batched benchmark shape (20,000 log-normal arrays around 2^14): every
-    split equals the oracle's count and every array is partitioned."""
+    """The batched benchmark shape (20,000 log-normal arrays around 2^14): for every
+    array the split equals the oracle's count, the array is partitioned and its own
+    multiset fingerprint is unchanged (so no element moved between arrays)."""
     lengths = workloads.lognormal_lengths(20000, workloads.config_seed(3))
     data, offsets, pivots = _batch("u64", lengths, workloads.config_seed(3))
     out, splits, st = _run_batched(ss, data, offsets, pivots)
-    for k in range(0, 20000, 7):
+    for k in range(20000):
         a, b = int(offsets[k]), int(offsets[k + 1])
-        assert int(splits[k]) == oracle.count_less(data[a:b], int(pivots[k]))
-        assert oracle.is_partitioned(out[a:b], int(pivots[k]), int(splits[k]))
-    assert oracle.fingerprint(out) == oracle.fingerprint(data)
+        assert int(splits[k]) == oracle.count_less(data[a:b], int(pivots[k])), k
+        assert oracle.is_partitioned(out[a:b], int(pivots[k]), int(splits[k])), k
+        assert oracle.fingerprint(out[a:b]) == oracle.fingerprint(data[a:b]), k
+    # sampled arrays element by element: both sides' sorted contents equal the oracle's
+    for k in range(0, 20000, 97):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        ref = data[a:b].copy()
+        rs = oracle.partition(ref, int(pivots[k]))
+        gl, gr = oracle.sorted_sides(out[a:b], rs)
+        rl, rr = oracle.sorted_sides(ref, rs)
+        assert np.array_equal(gl, rl) and np.array_equal(gr, rr), k
 
 
 def test_segments_any_order_with_gaps(ss):

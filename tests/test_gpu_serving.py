@@ -87,7 +87,7 @@ def test_engine_direct_jobs_and_capacity_flag(ss):
     eng.submit(10, 0, 0, 0, 0)          # empty partition: done at once
     eng.submit(11, 0, 1, 1, 0)          # one-record sort: done at once
     eng.tick(L)
-    eng.wait(0)
+    assert eng.wait(0) == 0
     assert eng.done(10)[0] and eng.done(11)[0]
     out = t.cpu().numpy().view(np.uint64)
     for k in range(4):
@@ -103,7 +103,7 @@ def test_engine_direct_jobs_and_capacity_flag(ss):
     for k in range(5):
         eng.submit(k, (k % n_jobs) * L, L, 0, pivots[k % n_jobs])
     eng.tick(L)
-    eng.wait(0)
+    assert eng.wait(0) & 1            # the mirrored flags show the overflow without a status call
     assert eng.status() & 1
     assert sum(eng.done(k)[0] for k in range(5)) == 4
     eng.close()
@@ -130,3 +130,58 @@ def test_serving_rejects_oversized_and_cancels(ss):
     assert sum(j.status == "done" for j in jobs) == 11
     assert srv.arena.used == 0 and srv.aux_used == 0 and len(srv.free_slots) == 4096
     assert latency_summary(jobs + [big, late])["jobs"] == 11
+
+
+def _check_job_by_payload(job, out):
+    """Exact check for large jobs without sorting records: the payload of a record
+    is its input position, so the output must be a permutation of the input
+    records (each payload once, each key still with its payload), with the
+    oracle's split and sides for a partition job and the oracle's key sequence
+    for a sort job."""
+    a0 = _input_of(job)
+    idx = out[:, 1] - np.uint64(job.job_id << 32)
+    assert bool(np.all(idx < np.uint64(job.n)))
+    seen = np.zeros(job.n, dtype=bool)
+    seen[idx.astype(np.int64)] = True
+    assert bool(seen.all())
+    assert np.array_equal(out[:, 0], a0[idx.astype(np.int64), 0])
+    if job.kind == "partition":
+        ref = a0.copy()
+        rs = oracle.partition(ref, job.pivot)
+        assert job.split == rs
+        assert oracle.is_partitioned(out, job.pivot, rs)
+    else:
+        ref = a0.copy()
+        oracle.quicksort(ref)
+        assert np.array_equal(out[:, 0], ref[:, 0])
+
+
+@pytest.mark.slow
+def test_serving_large_jobs_default_budget(ss):
+    """Jobs of 2^24 to 2^26 records (the upper end of the serving workload's length
+    range) mixed with small ones under the default 64 GiB budget; one large sort
+    job is also served alone and must give the same bytes."""
+    from paper_2004_12532_amd.serving import Job, Server, make_jobs
+    big = [("partition", 1 << 26, 0.5), ("sort", (1 << 25) + 3, 0.5), ("partition", (1 << 24) + 12345, 0.1),
+           ("sort", (1 << 24) + 777, 0.5), ("partition", (1 << 25) + 1, 0.93)]
+    jobs = [Job(job_id=200 + k, kind=kind, n=n, seed=(77 << 20) ^ k, arrival=0.0, quantile=q,
+                pivot=min((1 << 64) - 1, int(q * (1 << 64)))) for k, (kind, n, q) in enumerate(big)]
+    jobs += make_jobs(20, 0.0, 13, lo_log2=10.0, hi_log2=18.0)
+    srv = Server(keep_outputs=True)           # default budget: 64 GiB
+    srv.run(jobs, realtime=False)
+    for job in jobs:
+        assert job.status == "done"
+        if job.n >= 1 << 20:
+            _check_job_by_payload(job, srv.outputs[job.job_id])
+        else:
+            _check_job(job, srv.outputs[job.job_id])
+    solo_src = jobs[3]
+    solo = Job(job_id=solo_src.job_id, kind=solo_src.kind, n=solo_src.n, seed=solo_src.seed, arrival=0.0,
+               quantile=solo_src.quantile, pivot=solo_src.pivot)
+    mix_out = srv.outputs[solo_src.job_id]
+    del srv
+    import torch
+    torch.cuda.empty_cache()
+    s2 = Server(budget_bytes=4 << 30, keep_outputs=True)
+    s2.run([solo], realtime=False)
+    assert np.array_equal(s2.outputs[solo.job_id], mix_out)
