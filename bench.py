@@ -173,11 +173,7 @@ def run_partition(args, workload, algo="smoothed"):
     mean_level_ms = sum(level_ms) / len(level_ms)
     # The first level's algorithmic bytes: 2 n w in the stable form; in the
     # exchange form it reads n w and writes only the elements it stored.
-    first_bytes = alg_bytes
-    if stats["exchange_levels"]:
-        sizes = [hi - lo for lo, hi in zip(stats["level_lo"], stats["level_hi"])]
-        rest = sum((1 if l < stats["exchange_levels"] else 2) * w * sz for l, sz in enumerate(sizes) if l >= 1)
-        first_bytes = float(stats["bytes_moved"] - rest)
+    first_bytes = float(stats["first_level_bytes"])
     achieved = first_bytes / (mean_level_ms / 1e3) / 1e9
 
     probe = None
@@ -235,7 +231,7 @@ def run_partition(args, workload, algo="smoothed"):
                                    "exchange form)",
                         "hybrid": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step before the "
                                   "Low-Space pass over the middle, exchange form)"}.get(algo)
-                       if stats["exchange_levels"] else None) or
+                       if stats["exchange_mask"] & 1 else None) or
                       {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
                        "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
                        "lowspace": "whole Low-Space call (all its kernels)",

@@ -154,7 +154,7 @@ typedef struct ss_params {
     uint32_t b;           /* elements per cache line (the paper's b); b * sizeof(element) must be a
                              power of two between 64 and 4096 bytes.  Default: 512-byte lines. */
     uint32_t tile_bytes;  /* bytes of one group (s * b * sizeof(element) at most): 32768, 65536 or
-                             131072 (the last only with SS_ENGINE_REGS).  Default: chosen per engine. */
+                             131072 (the last only with SS_ENGINE_REGS or SS_ENGINE_STAGED).  Default: chosen per engine. */
     uint32_t max_levels;  /* recursion levels launched before the host looks at the result (1..32).
                              Default 8. */
     uint64_t seed;        /* seed of the random chunk offsets X_j; 0 selects a fixed default */
@@ -162,25 +162,33 @@ typedef struct ss_params {
     uint32_t engine;      /* workgroup body of a Partial Partition Step: SS_ENGINE_* (0 = auto) */
 } ss_params;
 
-/* Workgroup bodies of the Partial Partition Step.  Both compute the same
+/* Workgroup bodies of the Partial Partition Step.  All compute the same
  * stable partition of every group, so results are identical.
- * SS_ENGINE_LDS  : the group is permuted through an LDS tile and written back
- *                  as whole lines.
- * SS_ENGINE_REGS : the group stays in registers and every element is stored
- *                  straight to its destination (no LDS tile, higher occupancy).
- * SS_ENGINE_AUTO : SS_ENGINE_REGS with 131072-byte groups, except for SS_U32
- *                  in ss_partition / ss_partition_ex, which use SS_ENGINE_LDS
- *                  with 32768-byte groups (four 4-byte scattered stores per
- *                  16-byte vector cost more than staging through LDS).  The
- *                  batched calls and the serving engine use the register
- *                  engine with 131072-byte groups, and the LDS engine with
- *                  32768-byte groups for SS_U32; the quicksort's levels use
- *                  the LDS engine with 65536-byte groups for SS_U32.  An
- *                  explicit p->engine / tile_bytes overrides these.
- * Value 3 is reserved (rejected with SS_EINVAL). */
+ * SS_ENGINE_LDS    : the group is permuted through an LDS tile and written
+ *                    back as whole lines.
+ * SS_ENGINE_REGS   : the group stays in registers and every element is stored
+ *                    straight to its destination (no LDS tile, higher
+ *                    occupancy).
+ * SS_ENGINE_STAGED : the first level holds the group in registers, stages its
+ *                    stable partition in an LDS tile of the group's size and
+ *                    writes it back as whole lines while the next group's
+ *                    loads are in flight; later levels store from registers
+ *                    as SS_ENGINE_REGS does.
+ * In every stable body an element whose slot does not change is not stored.
+ * SS_ENGINE_AUTO   : SS_ENGINE_STAGED with 131072-byte groups in
+ *                    ss_partition / ss_partition_ex.  The batched calls and
+ *                    the serving engine use the register engine with
+ *                    131072-byte groups, and the LDS engine with 32768-byte
+ *                    groups for SS_U32 (four 4-byte scattered stores per
+ *                    16-byte vector cost more than staging through LDS); the
+ *                    quicksort's levels use the LDS engine with 65536-byte
+ *                    groups for SS_U32.  An explicit p->engine / tile_bytes
+ *                    overrides these; the batched calls take SS_ENGINE_STAGED
+ *                    as SS_ENGINE_REGS. */
 #define SS_ENGINE_AUTO 0u
 #define SS_ENGINE_LDS 1u
 #define SS_ENGINE_REGS 2u
+#define SS_ENGINE_STAGED 3u
 
 #define SS_MAX_LEVELS 32
 
@@ -204,8 +212,11 @@ typedef struct ss_stats {
     uint64_t bytes_moved;                /* algorithmic HBM bytes: 2 * elem_size * sum of level sizes; a
                                             level in the exchange form counts its reads and the elements
                                             it stored */
-    uint32_t exchange_levels;            /* leading levels run in the write-minimal exchange form */
-    uint32_t reserved;
+    uint32_t exchange_levels;            /* levels (of those listed) run in the write-minimal exchange form */
+    uint32_t exchange_mask;              /* bit l: listed level l ran in the exchange form (l < 32) */
+    uint64_t first_level_bytes;          /* algorithmic HBM bytes of the first level alone (2 * elem_size *
+                                            n, or n * elem_size plus the elements it stored in the
+                                            exchange form) */
 } ss_stats;
 
 /* Partition d_ptr[0, n) in place by key < pivot with Recursive Smoothed

@@ -76,7 +76,8 @@ class Stats(ctypes.Structure):
                 ("level_g", ctypes.c_uint32 * MAX_LEVELS), ("level_s", ctypes.c_uint32 * MAX_LEVELS),
                 ("vmin", ctypes.c_uint64), ("vmax", ctypes.c_uint64),
                 ("first_level_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
-                ("bytes_moved", ctypes.c_uint64), ("exchange_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("bytes_moved", ctypes.c_uint64), ("exchange_levels", ctypes.c_uint32), ("exchange_mask", ctypes.c_uint32),
+                ("first_level_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         nl = self.levels
@@ -87,6 +88,7 @@ class Stats(ctypes.Structure):
             "level_g": list(self.level_g[:nl]), "level_s": list(self.level_s[:nl]),
             "vmin": self.vmin, "vmax": self.vmax, "first_level_ms": self.first_level_ms,
             "total_ms": self.total_ms, "bytes_moved": self.bytes_moved, "exchange_levels": self.exchange_levels,
+            "exchange_mask": self.exchange_mask, "first_level_bytes": self.first_level_bytes,
         }
 
 
@@ -174,7 +176,7 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-ENGINES = {"auto": 0, "lds": 1, "regs": 2}
+ENGINES = {"auto": 0, "lds": 1, "regs": 2, "staged": 3}
 
 
 def make_params(algo="smoothed", b=0, tile_bytes=0, max_levels=0, seed=0, one_level=False, time=False,

@@ -164,14 +164,14 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
         return fail_msg(SS_EINVAL, "unknown algo");
     if (q.flags & ~(SS_FLAG_ONE_LEVEL | SS_FLAG_TIME | SS_FLAG_GRAPH | kExchangeFlags | SS_FLAG_STABLE))
         return fail_msg(SS_EINVAL, "unknown flags");
-    if (q.engine > SS_ENGINE_REGS)
+    if (q.engine > SS_ENGINE_STAGED)
         return fail_msg(SS_EINVAL, "unknown engine");
     uint32_t engine = q.engine ? q.engine : auto_engine;
     if (!q.engine && engine == SS_ENGINE_LDS && (q.tile_bytes == 131072u || (q.flags & kExchangeFlags)))
-        engine = SS_ENGINE_REGS;  // options only the register engine has
+        engine = SS_ENGINE_REGS;  // options only the register engines have
     const uint32_t tile = q.tile_bytes ? q.tile_bytes : engine == SS_ENGINE_LDS ? 32768u : kDefaultRegsTile;
-    if (tile != 32768u && tile != 65536u && !(tile == 131072u && engine == SS_ENGINE_REGS))
-        return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (register engine) 131072");
+    if (tile != 32768u && tile != 65536u && !(tile == 131072u && (engine == SS_ENGINE_REGS || engine == SS_ENGINE_STAGED)))
+        return fail_msg(SS_EINVAL, "tile_bytes must be 32768, 65536 or (register engines) 131072");
     if ((q.flags & kExchangeFlags) && engine == SS_ENGINE_LDS)
         return fail_msg(SS_EINVAL, "the write-minimal exchange applies to the register engine");
     const uint32_t b = q.b ? q.b : kDefaultLineBytes / w;
@@ -193,16 +193,19 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     r->flags = q.flags;
     // The automatic first-level choice needs the default geometry and the
     // register engine, and pays only for 8- and 16-byte elements.
-    r->auto_xch = !q.engine && !q.tile_bytes && !q.b && w >= 8 && engine == SS_ENGINE_REGS &&
+    r->auto_xch = !q.engine && !q.tile_bytes && !q.b && w >= 8 &&
+                  (engine == SS_ENGINE_REGS || engine == SS_ENGINE_STAGED) &&
                   !(q.flags & (kExchangeFlags | SS_FLAG_STABLE)) &&
                   (q.algo == SS_SMOOTHED || q.algo == SS_STRIDED || q.algo == SS_HYBRID);
     return SS_OK;
 }
 
-#define SS_LDS_VARIANT(D, T, NT, TB) {D, SS_ENGINE_LDS, TB, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr}
+#define SS_LDS_VARIANT(D, T, NT, TB) \
+    {D, SS_ENGINE_LDS, TB, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr, nullptr, nullptr}
 #define SS_RS_VARIANT(D, T, NT, NV)                                                                  \
     {D, SS_ENGINE_REGS, NT * NV * 16, NT, &launch_level_rs<T, NT, NV>, &level_rs_fn<T, NT, NV>, \
-     &launch_level_xch<T, NT, NV>, &level_xch_fn<T, NT, NV>}
+     &launch_level_xch<T, NT, NV>, &level_xch_fn<T, NT, NV>, &launch_level_staged<T, NT, NV>,     \
+     &level_staged_fn<T, NT, NV>}
 #define SS_RS_ALL(NT, NV) \
     SS_RS_VARIANT(SS_U32, uint32_t, NT, NV), SS_RS_VARIANT(SS_U64, uint64_t, NT, NV), SS_RS_VARIANT(SS_KV16, KV, NT, NV)
 
@@ -263,41 +266,51 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     rc = get_workspace(dev, st, &ws);
     if (rc)
         return rc;
-    const Variant *V = pick_variant(dtype, R.engine, R.tile);
+    auto grid_of = [&](const void *fn, int nt, size_t shmem, uint32_t *grid) -> int {
+        int occ = 0;
+        const int r = occupancy(dev, fn, nt, &occ, shmem);
+        const uint64_t g = (uint64_t)occ * (uint64_t)cus;
+        *grid = (uint32_t)(g < (uint64_t)kMaxGrid ? g : (uint64_t)kMaxGrid);
+        return r;
+    };
+    const bool staged = R.engine == SS_ENGINE_STAGED;
+    const uint32_t regs = staged ? (uint32_t)SS_ENGINE_REGS : R.engine;
+    const Variant *V = pick_variant(dtype, regs, R.tile);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
     // The exchange tables (16-bit slot numbers) are dynamic LDS.
     const bool xch = (R.flags & kExchangeFlags) != 0;
     if (xch && !V->fn_x)
         return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
-    int occ = 0;
-    rc = occupancy(dev, xch ? V->fn_x(true) : V->fn(true), V->nt, &occ, xch ? xch_lds_bytes(V->tile, R.w) : 0);
-    if (rc)
+    const bool xrest = xch;  // levels after the first in the exchange form
+    // The stable form of the first level: from registers, or staged in an LDS
+    // tile (the later levels store from registers).
+    auto launch_stable = staged ? V->launch_s : V->launch;
+    uint32_t P = 0, P1 = 0;
+    if ((rc = grid_of(xch ? V->fn_x(true) : staged ? V->fn_s(true) : V->fn(true), V->nt,
+                      xch ? xch_lds_bytes(V->tile, R.w) : staged ? (size_t)V->tile : 0, &P)))
         return rc;
-    uint32_t P = (uint32_t)(occ * cus);
-    if (P > (uint32_t)kMaxGrid)
-        P = kMaxGrid;
+    if ((rc = grid_of(xrest ? V->fn_x(false) : V->fn(false), V->nt, xrest ? xch_lds_bytes(V->tile, R.w) : 0, &P1)))
+        return rc;
     ro->grid = P;
     // Levels from the third on work on regions a few hundred times smaller
     // than the array; there a group is latency-bound, so they use 32 KiB
     // groups of 128-byte lines (more, shorter groups per level).
-    const Variant *Vt = pick_variant(dtype, R.engine, 32768u);
+    const Variant *Vt = pick_variant(dtype, regs, 32768u);
     if (!Vt)
         return fail_msg(SS_EUNSUPPORTED, "no tail kernel variant");
-    int occ_t = 0;
-    if (xch && !Vt->fn_x)
+    if (xrest && !Vt->fn_x)
         return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
-    rc = occupancy(dev, xch ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, &occ_t, xch ? xch_lds_bytes(Vt->tile, R.w) : 0);
-    if (rc)
+    uint32_t Pt = 0;
+    if ((rc = grid_of(xrest ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, xrest ? xch_lds_bytes(Vt->tile, R.w) : 0,
+                      &Pt)))
         return rc;
-    uint32_t Pt = (uint32_t)(occ_t * cus);
-    if (Pt > (uint32_t)kMaxGrid)
-        Pt = kMaxGrid;
     const uint32_t log2b_t = (uint32_t)ilog2(128 / R.w), s_max_t = 32768u / 128u;
     ro->aux_bytes = ws->bytes;
     ro->launches = 0;
-    ro->xch_levels = 0;
+    ro->xch_mask = 0;
     ro->written = 0;
+    ro->written0 = 0;
 
     // Automatic choice for large arrays: the first level is launched as a
     // pair, the stable form with the default groups and the exchange form
@@ -310,13 +323,8 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u);
         if (!Vx || !Vx->fn_x)
             return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
-        int occ_x = 0;
-        rc = occupancy(dev, Vx->fn_x(true), Vx->nt, &occ_x, xch_lds_bytes(Vx->tile, R.w));
-        if (rc)
+        if ((rc = grid_of(Vx->fn_x(true), Vx->nt, xch_lds_bytes(Vx->tile, R.w), &Px)))
             return rc;
-        Px = (uint32_t)(occ_x * cus);
-        if (Px > (uint32_t)kMaxGrid)
-            Px = kMaxGrid;
     }
 
     const bool timing = (R.flags & SS_FLAG_TIME) != 0;
@@ -345,10 +353,11 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         for (uint32_t k = 0; k < budget; k++, level++) {
             const bool first = k == 0;
             const bool tail = level >= 2;
+            const bool xl = xch || (level >= 1 && xrest);  // this level in the exchange form
             const Variant *Vl = tail ? Vt : V;
             a.log2b = tail ? log2b_t : R.log2b;
             a.s_max = tail ? s_max_t : R.s_max;
-            uint32_t grid = tail ? Pt : P;
+            uint32_t grid = tail ? Pt : level == 0 ? P : P1;
             if (first) {
                 const Geo G = plan_geo(lo, hi, a.log2b, a.s_max);
                 grid = G.g < grid ? G.g : grid;
@@ -370,15 +379,16 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                 if ((e = hipEventRecord(ws->ev[0], st)) != hipSuccess)
                     return fail_device(e, "hipEventRecord");
             }
-            if (xch)
-                a.written = ws->result + kResultWritten;
+            a.written = xl ? ws->result + (level == 0 ? kResultWrittenFirst : kResultWritten) : nullptr;
+            // without the sample kernel, the first level clears the count of stored elements
+            a.reset = level == 0 && !xch && !autox && xrest ? ws->result + kResultWritten : nullptr;
             if (level == 0 && autox) {
                 // the pair: stable form (gate 0), then exchange form (gate 1); the
                 // exchange form leaves the stable form's partial slots alone
                 a.gate = ws->result + kResultGate;
                 a.gate_want = 0;
                 a.gate_keep = 0;
-                if ((e = Vl->launch(first, grid, a, st)) != hipSuccess)
+                if ((e = launch_stable(first, grid, a, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 LevelArgs ax = a;
                 ax.s_max = (uint32_t)(Vx->tile / ((uint64_t)R.b * R.w));
@@ -386,7 +396,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                 const uint32_t grid_x = Gx.g < Px ? Gx.g : Px;
                 ax.gate_want = 1;
                 ax.gate_keep = grid;
-                ax.written = ws->result + kResultWritten;
+                ax.written = ws->result + kResultWrittenFirst;
                 if ((e = Vx->launch_x(first, grid_x, ax, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 ro->launches += 2;
@@ -394,9 +404,11 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                 a.written = nullptr;
                 grid = grid_x > grid ? grid_x : grid;
             } else {
-                if ((e = (xch ? Vl->launch_x : Vl->launch)(first, grid, a, st)) != hipSuccess)
+                if ((e = (xl ? Vl->launch_x : level == 0 ? launch_stable : Vl->launch)(first, grid, a, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 ro->launches++;
+                if (xl && level < 64)
+                    ro->xch_mask |= 1ull << level;
             }
             if (timing && level == 0) {
                 if ((e = hipEventRecord(ws->ev[1], st)) != hipSuccess)
@@ -437,13 +449,13 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         }
         ro->vmin = res[2];
         ro->vmax = res[3];
-        if (xch) {
-            ro->xch_levels = level;
-            ro->written = res[kResultWritten];
-        } else if (autox && res[kResultGate]) {
-            ro->xch_levels = 1;
-            ro->written = res[kResultWritten];
+        if (autox && res[kResultGate]) {
+            ro->xch_mask |= 1ull;
             ro->grid = Px;
+        }
+        if (ro->xch_mask) {
+            ro->written = res[kResultWritten] + ((ro->xch_mask & 1) ? res[kResultWrittenFirst] : 0);
+            ro->written0 = (ro->xch_mask & 1) ? res[kResultWrittenFirst] : 0;
         }
         if (res[0] || (R.flags & SS_FLAG_ONE_LEVEL)) {
             ro->done = res[0] != 0;
@@ -479,7 +491,7 @@ void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype)
     st->total_ms = ro.total_ms;
     st->lds_bytes = R.tile + R.tile / 64 * 4 + 1024;
     uint64_t moved = 0;
-    uint32_t lv = 0;
+    uint32_t lv = 0, xn = 0, xm = 0;
     for (uint32_t l = 0; l < ro.levels_run && l < (uint32_t)SS_MAX_LEVELS; l++) {
         if (ro.level_hi[l] > ro.level_lo[l]) {
             st->level_lo[lv] = ro.level_lo[l];
@@ -487,13 +499,22 @@ void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype)
             st->level_g[lv] = ro.level_g[l];
             st->level_s[lv] = ro.level_s[l];
             // a level in the exchange form reads its region and writes only what it stored
-            moved += (l < ro.xch_levels ? 1ull : 2ull) * elem_size(dtype) * (ro.level_hi[l] - ro.level_lo[l]);
+            const bool x = l < 64 && ((ro.xch_mask >> l) & 1);
+            moved += (x ? 1ull : 2ull) * elem_size(dtype) * (ro.level_hi[l] - ro.level_lo[l]);
+            if (x) {
+                xn++;
+                xm |= 1u << lv;
+            }
             lv++;
         }
     }
     st->levels = lv;
     st->bytes_moved = moved + (uint64_t)elem_size(dtype) * ro.written;
-    st->exchange_levels = ro.xch_levels;
+    st->exchange_levels = xn;
+    st->exchange_mask = xm;
+    if (ro.levels_run && ro.level_hi[0] > ro.level_lo[0])
+        st->first_level_bytes = (uint64_t)elem_size(dtype) * ((ro.xch_mask & 1) ? (ro.level_hi[0] - ro.level_lo[0]) + ro.written0
+                                                                             : 2 * (ro.level_hi[0] - ro.level_lo[0]));
 }
 
 }  // namespace ss
@@ -574,8 +595,8 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
     if (rc)
         return rc;
     Resolved R;
-    // single-array calls: u32 groups go through an LDS tile (see SS_ENGINE_AUTO)
-    rc = resolve_params(p, dtype, &R, dtype == SS_U32 ? (uint32_t)SS_ENGINE_LDS : kDefaultEngine);
+    // single-array calls: the first level is staged in LDS (see SS_ENGINE_AUTO)
+    rc = resolve_params(p, dtype, &R, SS_ENGINE_STAGED);
     if (rc)
         return rc;
     if (R.algo == SS_LOWSPACE || R.algo == SS_IMPLICIT)

@@ -90,6 +90,7 @@ struct LevelArgs {
     uint32_t gate_keep;     //   from workgroup gate_keep on (the other kernel of the pair wrote the rest)
     const uint64_t *gate;   // null: always run
     uint64_t *written;      // exchange form: elements stored, summed over the workgroups (null: not kept)
+    uint64_t *reset;        // first level: workgroup 0 clears this word at the start (null: none)
 };
 
 constexpr int kCtlWords = 8;        // words per level record

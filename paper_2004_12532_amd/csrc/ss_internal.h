@@ -24,7 +24,8 @@ constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a
 constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
 // LDS of the exchange form's slot table for groups of `tile` bytes of w-byte elements
 inline size_t xch_lds_bytes(uint32_t tile, int w) { return (size_t)tile / (uint32_t)w; }
-constexpr int kResultWritten = 6;   // result word: elements stored by exchange-form levels
+constexpr int kResultWrittenFirst = 5;  // result word: elements stored by a first level in the exchange form
+constexpr int kResultWritten = 6;   // result word: elements stored by later exchange-form levels
 constexpr int kResultGate = 7;      // result word: 1 when the exchange form was chosen
 
 struct Workspace {
@@ -60,8 +61,9 @@ struct RunOut {
     uint32_t launches;
     uint64_t aux_bytes;
     float first_level_ms, total_ms;
-    uint32_t xch_levels;   // leading levels run in the exchange form
+    uint64_t xch_mask;     // bit l: level l ran in the exchange form
     uint64_t written;      // elements those levels stored
+    uint64_t written0;     // of which the first level stored
     uint64_t level_lo[SS_MAX_LEVELS], level_hi[SS_MAX_LEVELS];
     uint32_t level_g[SS_MAX_LEVELS], level_s[SS_MAX_LEVELS];
 };
@@ -76,6 +78,9 @@ struct Variant {
     // the write-minimal exchange form (register engines; null for the LDS engine)
     hipError_t (*launch_x)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
     const void *(*fn_x)(bool first);
+    // the stable form staged in an LDS tile (register engines; null for the LDS engine)
+    hipError_t (*launch_s)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+    const void *(*fn_s)(bool first);
 };
 
 template <typename T, int NT, int TB>
@@ -86,6 +91,10 @@ template <typename T, int NT, int NV>
 hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int NV>
 const void *level_rs_fn(bool first);
+template <typename T, int NT, int NV>
+hipError_t launch_level_staged(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+template <typename T, int NT, int NV>
+const void *level_staged_fn(bool first);
 template <typename T, int NT, int NV>
 hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int NV>

@@ -41,9 +41,16 @@
 
 namespace ss {
 
-template <typename T, int NT, int NV, bool FIRST, bool XCH>
+// Forms of the step's store: every element stored to its slot from
+// registers, the write-minimal exchange, or the stable partition staged in
+// an LDS tile and written back as whole lines.
+enum { kFormDirect = 0, kFormExchange = 1, kFormStaged = 2 };
+
+template <typename T, int NT, int NV, bool FIRST, int FORM>
 __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 {
+    constexpr bool XCH = FORM == kFormExchange;
+    constexpr bool STAGED = FORM == kFormStaged;
     using Ctx = LevelCtx<T, NT, NV>;
     constexpr int W = Ctx::W;
     constexpr int NW = Ctx::NW;
@@ -56,6 +63,8 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 
     const int tid = threadIdx.x;
     const uint32_t bid = blockIdx.x;
+    if (FIRST && a.reset && bid == 0 && tid == 0)
+        *a.reset = 0ull;
 
     // A first level launched as one of a stable/exchange pair: the kernel the
     // gate word does not select only leaves neutral partials behind.
@@ -133,7 +142,9 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             x.template load<false>(buf, i, m);
         return f;
     };
-    extern __shared__ uint16_t xt[];  // Ctx::XCH_BYTES: the exchange table (exchange form)
+    // dynamic LDS: the exchange table (Ctx::XCH_BYTES) or the staging tile (NVEC vectors)
+    extern __shared__ v4u dyn_lds[];
+    uint16_t *const xt = reinterpret_cast<uint16_t *>(dyn_lds);
     uint64_t written = 0;             // exchange form: elements this workgroup stored
     auto part_any = [&](const v4u (&buf)[NV], uint32_t i, bool f, const Mask &m) -> uint32_t {
         if constexpr (XCH)
@@ -144,7 +155,9 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     };
 
     // One register buffer: the next group's loads are issued right after this
-    // group's stores, before the barrier that lets the counts be rewritten.
+    // group's stores (staged form: right after the tile is complete, ahead of
+    // the tile's write-back), before the barrier that lets the counts be
+    // rewritten.
     const uint32_t step = gridDim.x;
     v4u buf[NV];
     Mask m;
@@ -153,11 +166,27 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     if (i < G.g)
         fast = load_any(buf, i, m);
     while (i < G.g) {
-        fold(part_any(buf, i, fast, m), i);
-        i += step;
-        if (i < G.g)
-            fast = load_any(buf, i, m);
-        __syncthreads();  // the counts are rewritten by the next group
+        if constexpr (STAGED) {
+            const uint32_t c = fast ? x.template stage<true>(buf, m, dyn_lds) : x.template stage<false>(buf, m, dyn_lds);
+            fold(c, i);
+            __syncthreads();  // the tile is complete
+            const bool fast_cur = fast;
+            const Mask m_cur = m;
+            const uint32_t icur = i;
+            i += step;
+            if (i < G.g)
+                fast = load_any(buf, i, m);
+            if (fast_cur)
+                x.template write_back<true>(dyn_lds, icur, m_cur);
+            else
+                x.template write_back<false>(dyn_lds, icur, m_cur);
+        } else {
+            fold(part_any(buf, i, fast, m), i);
+            i += step;
+            if (i < G.g)
+                fast = load_any(buf, i, m);
+        }
+        __syncthreads();  // the counts (and the staging tile) are rewritten by the next group
     }
     if (tid == 0) {
         a.out[2 * bid] = vmin;
@@ -167,29 +196,37 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     }
 }
 
-template <typename T, int NT, int NV, bool XCH>
+template <typename T, int NT, int NV, int FORM>
 const void *level_rs_fn_t(bool first)
 {
-    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, XCH>)
-                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, XCH>);
+    return first ? reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, true, FORM>)
+                 : reinterpret_cast<const void *>(&k_level_rs<T, NT, NV, false, FORM>);
 }
 
-// Launch of the stable form (XCH = false) or the exchange form (XCH = true),
-// whose table of slot numbers is dynamic LDS.
-template <typename T, int NT, int NV, bool XCH>
+// Dynamic LDS of a form: the exchange form's table of slot numbers, or the
+// staged form's tile of one group.
+template <typename T, int NT, int NV, int FORM>
+constexpr size_t level_rs_lds()
+{
+    return FORM == kFormExchange ? LevelCtx<T, NT, NV>::XCH_BYTES
+           : FORM == kFormStaged ? (size_t)LevelCtx<T, NT, NV>::NVEC * 16
+                                 : 0;
+}
+
+template <typename T, int NT, int NV, int FORM>
 hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
 {
-    const size_t shmem = XCH ? LevelCtx<T, NT, NV>::XCH_BYTES : 0;
+    constexpr size_t shmem = level_rs_lds<T, NT, NV, FORM>();
     if (shmem > 32768) {
-        const hipError_t e = hipFuncSetAttribute(level_rs_fn_t<T, NT, NV, XCH>(first),
+        const hipError_t e = hipFuncSetAttribute(level_rs_fn_t<T, NT, NV, FORM>(first),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess)
             return e;
     }
     if (first)
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, true, FORM>), dim3(grid), dim3(NT), shmem, st, a);
     else
-        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, XCH>), dim3(grid), dim3(NT), shmem, st, a);
+        hipLaunchKernelGGL((k_level_rs<T, NT, NV, false, FORM>), dim3(grid), dim3(NT), shmem, st, a);
     return hipGetLastError();
 }
 

@@ -10,13 +10,13 @@ namespace ss {
 template <typename T, int NT, int NV>
 hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
 {
-    return launch_level_rs_t<T, NT, NV, true>(first, grid, a, st);
+    return launch_level_rs_t<T, NT, NV, kFormExchange>(first, grid, a, st);
 }
 
 template <typename T, int NT, int NV>
 const void *level_xch_fn(bool first)
 {
-    return level_rs_fn_t<T, NT, NV, true>(first);
+    return level_rs_fn_t<T, NT, NV, kFormExchange>(first);
 }
 
 #define SS_INSTANTIATE_XCH(T, NT, NV)                                                              \
@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(kPrepNT) k_xch_prepare(const T *A, uint64_t n,
         const bool skewed = c * den <= kSkewSamples || c * den >= (den - 1) * kSkewSamples;
         result[kResultGate] = force || skewed ? 1ull : 0ull;
         result[kResultWritten] = 0ull;
+        result[kResultWrittenFirst] = 0ull;
     }
 }
 

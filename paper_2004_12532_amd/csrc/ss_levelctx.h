@@ -188,14 +188,19 @@ struct LevelCtx {
         return elem_ptr(((uint64_t)line_of(d >> log2b, i) << log2b) + (d & (b - 1)));
     }
 
-    // Store every real element at its slot of the stable partition.
+    // Store every real element at its slot of the stable partition.  An
+    // element whose slot does not change is not stored: in a region that is
+    // already nearly partitioned (the middle region a level leaves behind)
+    // the slots before the first misplaced element and after the last one
+    // keep their elements, so their lines are only read.
     template <bool FAST>
     __device__ __forceinline__ void store_stable(const v4u (&buf)[NV], uint32_t i, const Mask &m, uint64_t pb,
                                                  uint32_t c) const
     {
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
-            if (FAST || ((m.real >> (r * V + e)) & 1))
-                Elem<T>::store1(buf[r], e, slot_ptr(p ? rp : c + slot - rp, i));
+            const uint32_t d = p ? rp : c + slot - rp;
+            if ((FAST || ((m.real >> (r * V + e)) & 1)) && d != slot)
+                Elem<T>::store1(buf[r], e, slot_ptr(d, i));
         });
     }
 
@@ -207,6 +212,51 @@ struct LevelCtx {
         const uint32_t c = cnt[E];
         store_stable<FAST>(buf, i, m, pb, c);
         return c;
+    }
+
+    // Staged form of the stable partition: every real element goes to its
+    // slot of an LDS tile of NVEC vectors (slot order), from which
+    // write_back later stores whole lines.  Virtual slots stay unwritten:
+    // virtual predecessors are a prefix and virtual successors a suffix of
+    // the slot sequence, so the stable partition leaves them in place.
+    // Returns c_i.
+    template <bool FAST>
+    __device__ __forceinline__ uint32_t stage(const v4u (&buf)[NV], const Mask &m, v4u *tile) const
+    {
+        const uint64_t pb = count<FAST>(buf, m);
+        const uint32_t c = cnt[E];
+        for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
+            if (FAST || ((m.real >> (r * V + e)) & 1))
+                Elem<T>::put(tile, p ? rp : c + slot - rp, buf[r], e);
+        });
+        return c;
+    }
+
+    // Store the staged tile of group i to the group's lines: thread tid
+    // stores the vectors it loaded, so every wavefront store covers whole
+    // lines.  A vector that is not wholly real (general path only) is
+    // stored element by element.
+    template <bool FAST>
+    __device__ __forceinline__ void write_back(const v4u *tile, uint32_t i, const Mask &m) const
+    {
+        constexpr uint32_t VM = (1u << V) - 1;
+#pragma unroll
+        for (int r = 0; r < NV; r++) {
+            const uint32_t q = r * NT + tid;
+            if (!FAST && q >= nvec)
+                continue;
+            const v4u v = tile[q];
+            char *const p = elem_ptr(vec_start(q, i));
+            const uint32_t real = FAST ? VM : (uint32_t)(m.real >> (r * V)) & VM;
+            if (real == VM) {
+                *reinterpret_cast<v4u *>(p) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; e++)
+                    if ((real >> e) & 1)
+                        Elem<T>::store1(v, e, p + e * W);
+            }
+        }
     }
 
     // Slots of the exchange table: a group has at most S / 2 misplaced pairs.

@@ -32,8 +32,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import paper_2004_12532_amd as ss
     assert ctypes.sizeof(ss.Params) == 32
-    # split, aux, 6 x u32, 2 x 32 x u64, 2 x 32 x u32, vmin, vmax, 2 floats, bytes_moved, 2 x u32
-    assert ctypes.sizeof(ss.Stats) == 8 + 8 + 24 + 2 * 32 * 8 + 2 * 32 * 4 + 16 + 8 + 8 + 8
+    # split, aux, 6 x u32, 2 x 32 x u64, 2 x 32 x u32, vmin, vmax, 2 floats, bytes_moved, 2 x u32,
+    # first_level_bytes
+    assert ctypes.sizeof(ss.Stats) == 8 + 8 + 24 + 2 * 32 * 8 + 2 * 32 * 4 + 16 + 8 + 8 + 8 + 8
     # nclass, 8 x b, 8 x group_bytes, (pad), 8 x max_len, 8 x ms
     assert ctypes.sizeof(ss.Tuning) == 4 + 32 + 32 + 4 + 64 + 32
 

@@ -66,7 +66,7 @@ def test_config1_median_u64(ss):
 SIZES = [1, 2, 3, 15, 16, 17, 31, 127, 128, 129, 1000, 8191, 8192, 8193, 16385, 65535, 65537, 100003, 300001]
 
 
-ENGINES = ["lds", "regs"]
+ENGINES = ["lds", "regs", "staged"]
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -206,6 +206,10 @@ def test_engines_give_identical_bytes(ss, kind):
         s2 = ss.partition(t2, p, engine="regs", tile_bytes=tile, seed=5)
         assert s1 == s2
         assert bool((t1 == t2).all())
+        t3 = to_device(a0)
+        s3 = ss.partition(t3, p, engine="staged", tile_bytes=tile, seed=5)
+        assert s3 == s1
+        assert bool((t3 == t1).all())
 
 
 def test_small_level_budget_continues_from_host(ss):
@@ -462,7 +466,7 @@ def test_automatic_exchange_choice(ss, kind):
         p = workloads.pivot_at_quantile_np(a0, q)
         t = to_device(a0)
         split, st = ss.partition(t, p, stats=True)
-        assert st["exchange_levels"] == want, (q, st["exchange_levels"])
+        assert st["exchange_mask"] & 1 == want, (q, st["exchange_mask"])
         out = to_host(t, a0)
         ref = a0.copy()
         assert split == oracle.partition(ref, p)
@@ -475,7 +479,7 @@ def test_automatic_exchange_choice(ss, kind):
             assert st["bytes_moved"] < 2 * n * w
         t2 = to_device(a0)
         split2, st2 = ss.partition(t2, p, stats=True, exchange=False)
-        assert split2 == split and st2["exchange_levels"] == 0
+        assert split2 == split and st2["exchange_levels"] == 0 and st2["exchange_mask"] == 0
         t3 = to_device(a0)
         ss.partition(t3, p)
         assert bool((t3 == t).all())   # the choice depends only on the input
@@ -487,7 +491,7 @@ def test_automatic_exchange_strided_and_hybrid(ss):
     for algo in ("strided", "hybrid"):
         t = to_device(a0)
         split, st = ss.partition(t, p, stats=True, algo=algo)
-        assert st["exchange_levels"] == 1, algo
+        assert st["exchange_mask"] & 1 == 1, algo
         out = to_host(t, a0)
         ref = a0.copy()
         assert split == oracle.partition(ref, p)
