@@ -109,7 +109,7 @@ enum ss_status {
     SS_ENOMEM = -2,        /* device workspace allocation failed */
     SS_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
     SS_EUNSUPPORTED = -4,  /* valid but unsupported combination (e.g. an algorithm not offered for a dtype) */
-    SS_EINCOMPLETE = -5    /* asynchronous call: the device-side recursion budget ran out (see ss_partition_ex) */
+    SS_EINCOMPLETE = -5    /* reserved: the recursion ended without a result */
 };
 
 /* Flags for ss_params.flags. */
@@ -155,8 +155,10 @@ typedef struct ss_params {
                              power of two between 64 and 4096 bytes.  Default: 512-byte lines. */
     uint32_t tile_bytes;  /* bytes of one group (s * b * sizeof(element) at most): 32768, 65536 or
                              131072 (the last only with SS_ENGINE_REGS or SS_ENGINE_STAGED).  Default: chosen per engine. */
-    uint32_t max_levels;  /* recursion levels launched before the host looks at the result (1..32).
-                             Default 8. */
+    uint32_t max_levels;  /* Partial Partition Steps of the recursion (1..32), after which the
+                             serial base case (one workgroup) partitions what is left.  Default:
+                             planned from n, so that the region left is expected to take the base
+                             case at most two passes. */
     uint64_t seed;        /* seed of the random chunk offsets X_j; 0 selects a fixed default */
     uint32_t flags;       /* SS_FLAG_* */
     uint32_t engine;      /* workgroup body of a Partial Partition Step: SS_ENGINE_* (0 = auto) */
@@ -230,12 +232,11 @@ int ss_partition(void *d_ptr, size_t n, int dtype, uint64_t pivot, size_t *split
  *            the stream (asynchronous when h_split and stats are NULL);
  *   h_split (host, nullable):   receives the split (call synchronizes);
  *   stats   (host, nullable):   per-level record (call synchronizes).
- * If h_split and stats are both NULL the call does not synchronize; if the
- * device-side recursion does not finish within max_levels levels (which for
- * the default budget needs a run of improbable random offsets), *d_split is
- * set to UINT64_MAX and the caller must repeat the call.  A synchronizing
- * call never returns SS_EINCOMPLETE: it continues the recursion from the
- * host until it finishes. */
+ * If h_split and stats are both NULL the call does not synchronize.  Every
+ * call finishes on the device: the recursion's serial base case partitions
+ * whatever region the planned levels leave (a larger region takes it
+ * longer), so SS_EINCOMPLETE is not returned by partition calls.
+ * SS_FLAG_ONE_LEVEL stops after the first level instead (no base case). */
 int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_params *p,
                     void *stream, uint64_t *d_split, size_t *h_split, ss_stats *stats);
 
@@ -391,7 +392,9 @@ const char *ss_last_error(void);
 /* Memory-bandwidth probe over d_ptr[0, bytes) (bytes a multiple of 16), the
  * GPU counterpart of the paper's bandwidth measurements (Section 5.1, "The
  * Memory-Bandwidth Limitation"): mode 0 reads every byte once, mode 1 reads
- * every 16-byte word and immediately overwrites it with the same value.
+ * every 16-byte word and immediately overwrites it with the same value
+ * (grid-stride), mode 2 does the same with every workgroup walking one
+ * contiguous block of the buffer (the attainable in-place read/write rate).
  * *ms receives the kernel duration (blocking). */
 int ss_probe_bandwidth(void *d_ptr, size_t bytes, int mode, void *stream, float *ms);
 

@@ -378,7 +378,8 @@ def aux_bytes(n: int, dtype: int, algo="smoothed") -> int:
 
 
 def probe_bandwidth(t, mode: int, stream=None) -> float:
-    """Duration in ms of the read (mode 0) or read/overwrite (mode 1) probe over the tensor's bytes."""
+    """Duration in ms of the read (mode 0), grid-stride read/overwrite (mode 1) or contiguous-block
+    read/overwrite (mode 2) probe over the tensor's bytes."""
     ms = ctypes.c_float(0)
     nbytes = t.numel() * t.element_size()
     _check(_lib.ss_probe_bandwidth(ctypes.c_void_p(t.data_ptr()), nbytes, mode, _stream(stream),

@@ -7,6 +7,7 @@
 // the device-side level budget runs out, and the per-call statistics.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -178,7 +179,7 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
     const uint64_t line = (uint64_t)b * w;
     if (b == 0 || (b & (b - 1)) || line < 64 || line > 4096 || line > tile)
         return fail_msg(SS_EINVAL, "b * sizeof(element) must be a power of two in [64, 4096] bytes");
-    const uint32_t levels = q.max_levels ? q.max_levels : kDefaultLevels;
+    const uint32_t levels = q.max_levels;  // 0: planned per call from n (planned_levels)
     if (levels > (uint32_t)kMaxLevels)
         return fail_msg(SS_EINVAL, "max_levels above 32");
     r->algo = q.algo;
@@ -245,6 +246,29 @@ int check_lines(uint64_t n, const Resolved &R)
     if ((n + 2ull * R.b) / R.b >= (1ull << 32))
         return fail_msg(SS_EINVAL, "array has 2^32 lines or more for this b; use longer lines");
     return SS_OK;
+}
+
+// Partial Partition Steps a call runs before its serial base case.  The
+// first level leaves a middle region of about 4.4 / sqrt(S) of the array
+// (S elements per group: the groups' predecessor counts spread about 4.4
+// standard deviations each way around their mean, times g groups); each
+// later level (32 KiB groups of 128-byte lines on a region that is already
+// nearly partitioned) leaves about a ninth of its region.  The plan stops
+// once the expected region is at most two of the base case's passes; the
+// base case partitions whatever is left, so the plan affects only time.
+uint32_t planned_levels(uint64_t n, const Resolved &R)
+{
+    const uint64_t S0 = (uint64_t)R.s_max << R.log2b;
+    if (n <= S0)
+        return 1;
+    const double base = 2.0 * (double)cleanup_pass_elems(R.w);
+    double r = (double)n * 4.4 / std::sqrt((double)S0);
+    uint32_t lv = 1;
+    while (r > base && lv < (uint32_t)kMaxLevels) {
+        r *= 0.11;
+        lv++;
+    }
+    return lv;
 }
 
 // Run the recursion of Smoothed Striding (or the single Strided step) on
@@ -329,7 +353,8 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
 
     const bool timing = (R.flags & SS_FLAG_TIME) != 0;
     const bool strided = R.algo == SS_STRIDED;
-    const uint32_t budget = (R.flags & SS_FLAG_ONE_LEVEL) || strided ? 1u : R.levels;
+    const bool one_level = (R.flags & SS_FLAG_ONE_LEVEL) != 0;
+    const uint32_t budget = one_level || strided ? 1u : R.levels ? R.levels : planned_levels(n, R);
 
     uint64_t lo = 0, hi = n;
     uint32_t level = 0;  // global level index (fresh offsets per level)
@@ -419,10 +444,11 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             prev_count = grid;
         }
         uint64_t *host = sync ? ws->host_dev : nullptr;
-        if (strided && !(R.flags & SS_FLAG_ONE_LEVEL)) {
-            // Serial Cleanup Step: one workgroup partitions [v_min, v_max).
-            if ((e = launch_cleanup(dtype, base, pivot, prev, prev_count, ws->result, d_split, ws->ctl, host, st)) !=
-                hipSuccess)
+        if (!one_level) {
+            // The serial base case (Recursive Smoothed Striding) or the Serial
+            // Cleanup Step (Strided): one workgroup partitions [v_min, v_max).
+            if ((e = launch_cleanup(dtype, base, pivot, prev, prev_count, ws->result, d_split, ws->ctl, budget, host,
+                                    st)) != hipSuccess)
                 return fail_device(e, "cleanup kernel launch");
             ro->launches++;
         } else {

@@ -18,7 +18,6 @@ constexpr uint32_t kHostLevelCap = 512;
 constexpr uint32_t kDefaultEngine = SS_ENGINE_REGS;
 constexpr uint32_t kDefaultRegsTile = 131072;
 constexpr uint32_t kDefaultLineBytes = 512;
-constexpr uint32_t kDefaultLevels = 8;
 constexpr uint32_t kExchangeFlags = SS_FLAG_EXCHANGE | SS_FLAG_EXCHANGE_SKEWED;
 constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a group's slots
 constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
@@ -105,7 +104,9 @@ hipError_t launch_xch_prepare(int dtype, const char *base, uint64_t n, uint64_t 
 hipError_t launch_finish(const uint64_t *prev, uint32_t count, const uint64_t *prev_ctl, uint64_t *result,
                          uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host, hipStream_t st);
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
-                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint64_t *host, hipStream_t st);
+                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host,
+                          hipStream_t st);
+uint64_t cleanup_pass_elems(int w);  // elements the serial base case partitions in one pass
 
 int fail_device(hipError_t e, const char *what);
 int fail_msg(int code, const std::string &msg);
@@ -120,6 +121,7 @@ int get_workspace(int dev, void *stream, Workspace **out);
 void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
                   uint64_t *d_split, bool sync, RunOut *ro);
+uint32_t planned_levels(uint64_t n, const Resolved &R);
 
 // Size classes of a batched call: arrays of length <= max_len[c] (and above
 // the previous class's bound) use lines of 2^log2b[c] elements and groups of

@@ -14,7 +14,7 @@ namespace ss {
 template <typename T, int NT, int BB>
 __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, const uint64_t *prev,
                                                  uint32_t count, uint64_t *result, uint64_t *d_split,
-                                                 const uint64_t *ctl, uint64_t *host)
+                                                 const uint64_t *ctl, uint32_t nctl, uint64_t *host)
 {
     constexpr int NW = NT / 64;
     __shared__ CleanupSmem<T, NT, BB> S;
@@ -40,28 +40,34 @@ __global__ void __launch_bounds__(NT) k_cleanup(char *base, uint64_t pivot, cons
             host[3] = hi;
         }
     }
-    if (host && tid < kCtlWords)
-        host[kResultWordsDev + tid] = ctl[tid];
+    if (host)
+        for (uint32_t k = tid; k < nctl * kCtlWords; k += NT)
+            host[kResultWordsDev + k] = ctl[k];
     if (host && tid >= 4 && tid < kResultWordsDev)
         host[tid] = result[tid];
 }
 
+constexpr int kCleanupNT = 1024, kCleanupBB = 32768;  // 32 KiB blocks: twice the bytes per serial step of 16 KiB
+
+uint64_t cleanup_pass_elems(int w) { return 2ull * kCleanupBB / (uint64_t)w; }
+
 hipError_t launch_cleanup(int dtype, char *base, uint64_t pivot, const uint64_t *prev, uint32_t count,
-                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint64_t *host, hipStream_t st)
+                          uint64_t *result, uint64_t *d_split, const uint64_t *ctl, uint32_t nctl, uint64_t *host,
+                          hipStream_t st)
 {
-    constexpr int NT = 1024, BB = 32768;  // 32 KiB blocks: twice the bytes per serial step of 16 KiB ones
+    constexpr int NT = kCleanupNT, BB = kCleanupBB;
     switch (dtype) {
     case SS_U32:
         hipLaunchKernelGGL((k_cleanup<uint32_t, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count,
-                           result, d_split, ctl, host);
+                           result, d_split, ctl, nctl, host);
         break;
     case SS_U64:
         hipLaunchKernelGGL((k_cleanup<uint64_t, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count,
-                           result, d_split, ctl, host);
+                           result, d_split, ctl, nctl, host);
         break;
     default:
         hipLaunchKernelGGL((k_cleanup<KV, NT, BB>), dim3(1), dim3(NT), 0, st, base, pivot, prev, count, result,
-                           d_split, ctl, host);
+                           d_split, ctl, nctl, host);
         break;
     }
     return hipGetLastError();

@@ -212,13 +212,35 @@ def test_engines_give_identical_bytes(ss, kind):
         assert bool((t3 == t1).all())
 
 
-def test_small_level_budget_continues_from_host(ss):
+def test_small_level_budget_ends_in_base_case(ss):
+    """With a level budget below the plan, the serial base case partitions the
+    larger region the levels leave, asynchronously as well."""
+    torch = _torch()
     a0 = workloads.keys_u64(1 << 20, 3)
     p = workloads.pivot_at_quantile_np(a0, 0.5)
-    _, split = check_against_oracle(ss, a0, p, max_levels=1)
+    for lv in (1, 2):
+        _, split = check_against_oracle(ss, a0, p, max_levels=lv)
+        t = to_device(a0)
+        split2, st = ss.partition(t, p, stats=True, max_levels=lv)
+        assert split2 == split and st["levels"] == lv
+        assert st["vmax"] - st["vmin"] > 0  # the base case had a region to finish
+        t = to_device(a0)
+        d = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+        ss.partition_async(t, p, d, max_levels=lv)
+        torch.cuda.synchronize()
+        assert int(d.item()) == split
+
+
+def test_planned_levels_leave_small_base_case(ss):
+    """The default plan for 2^20 keys leaves the base case a region that one
+    or two of its passes finish (parity pinned by the oracle check)."""
+    a0 = workloads.keys_u64(1 << 20, 8)
+    p = workloads.pivot_at_quantile_np(a0, 0.5)
+    check_against_oracle(ss, a0, p)
     t = to_device(a0)
-    split2, st = ss.partition(t, p, stats=True, max_levels=1)
-    assert split2 == split and st["levels"] >= 2
+    split, st = ss.partition(t, p, stats=True)
+    assert 1 <= st["levels"] <= 4
+    assert st["vmax"] - st["vmin"] <= 4 * 8192
 
 
 def test_async_split_and_empty(ss):
