@@ -202,11 +202,17 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
 }
 
 #define SS_LDS_VARIANT(D, T, NT, TB) \
-    {D, SS_ENGINE_LDS, TB, NT, &launch_level<T, NT, TB>, &level_fn<T, NT, TB>, nullptr, nullptr, nullptr, nullptr}
-#define SS_RS_VARIANT(D, T, NT, NV)                                                                  \
-    {D, SS_ENGINE_REGS, NT * NV * 16, NT, &launch_level_rs<T, NT, NV>, &level_rs_fn<T, NT, NV>, \
-     &launch_level_xch<T, NT, NV>, &level_xch_fn<T, NT, NV>, &launch_level_staged<T, NT, NV>,     \
-     &level_staged_fn<T, NT, NV>}
+    {D, SS_ENGINE_LDS, TB, NT, {&launch_level<T, NT, TB>}, {&level_fn<T, NT, TB>}, {0}}
+#define SS_RS_FORMS(F, T, NT, NV) {F<T, NT, NV, kFormDirect>, F<T, NT, NV, kFormExchange>, F<T, NT, NV, kFormStaged>}
+#define SS_RS_VARIANT(D, T, NT, NV)                                                                        \
+    {D,                                                                                                    \
+     SS_ENGINE_REGS,                                                                                       \
+     NT * NV * 16,                                                                                         \
+     NT,                                                                                                   \
+     SS_RS_FORMS(&launch_level_rs_t, T, NT, NV),                                                          \
+     SS_RS_FORMS(&level_rs_fn_t, T, NT, NV),                                                              \
+     {level_form_lds<T, NT, NV, kFormDirect>(), level_form_lds<T, NT, NV, kFormExchange>(),              \
+      level_form_lds<T, NT, NV, kFormStaged>()}}
 #define SS_RS_ALL(NT, NV) \
     SS_RS_VARIANT(SS_U32, uint32_t, NT, NV), SS_RS_VARIANT(SS_U64, uint64_t, NT, NV), SS_RS_VARIANT(SS_KV16, KV, NT, NV)
 
@@ -302,32 +308,28 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const Variant *V = pick_variant(dtype, regs, R.tile);
     if (!V)
         return fail_msg(SS_EUNSUPPORTED, "no kernel variant for dtype/tile");
-    // The exchange tables (16-bit slot numbers) are dynamic LDS.
+    // Store forms: the first level's (exchange if forced, else stable from
+    // registers or staged in LDS), the second level's and the later levels'.
     const bool xch = (R.flags & kExchangeFlags) != 0;
-    if (xch && !V->fn_x)
+    const int f0 = xch ? kFormExchange : staged ? kFormStaged : kFormDirect;
+    const int f1 = xch ? kFormExchange : kFormDirect;
+    const int ft = f1;
+    if (!V->launch[f0] || !V->launch[f1])
         return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
-    const bool xrest = xch;  // levels after the first in the exchange form
-    // The stable form of the first level: from registers, or staged in an LDS
-    // tile (the later levels store from registers).
-    auto launch_stable = staged ? V->launch_s : V->launch;
     uint32_t P = 0, P1 = 0;
-    if ((rc = grid_of(xch ? V->fn_x(true) : staged ? V->fn_s(true) : V->fn(true), V->nt,
-                      xch ? xch_lds_bytes(V->tile, R.w) : staged ? (size_t)V->tile : 0, &P)))
+    if ((rc = grid_of(V->fn[f0](true), V->nt, V->lds[f0], &P)))
         return rc;
-    if ((rc = grid_of(xrest ? V->fn_x(false) : V->fn(false), V->nt, xrest ? xch_lds_bytes(V->tile, R.w) : 0, &P1)))
+    if ((rc = grid_of(V->fn[f1](false), V->nt, V->lds[f1], &P1)))
         return rc;
     ro->grid = P;
     // Levels from the third on work on regions a few hundred times smaller
     // than the array; there a group is latency-bound, so they use 32 KiB
     // groups of 128-byte lines (more, shorter groups per level).
     const Variant *Vt = pick_variant(dtype, regs, 32768u);
-    if (!Vt)
+    if (!Vt || !Vt->launch[ft])
         return fail_msg(SS_EUNSUPPORTED, "no tail kernel variant");
-    if (xrest && !Vt->fn_x)
-        return fail_msg(SS_EUNSUPPORTED, "the write-minimal exchange needs a register engine");
     uint32_t Pt = 0;
-    if ((rc = grid_of(xrest ? Vt->fn_x(false) : Vt->fn(false), Vt->nt, xrest ? xch_lds_bytes(Vt->tile, R.w) : 0,
-                      &Pt)))
+    if ((rc = grid_of(Vt->fn[ft](false), Vt->nt, Vt->lds[ft], &Pt)))
         return rc;
     const uint32_t log2b_t = (uint32_t)ilog2(128 / R.w), s_max_t = 32768u / 128u;
     ro->aux_bytes = ws->bytes;
@@ -342,12 +344,13 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     // word that makes exactly one of them run.
     const bool autox = R.auto_xch && n >= kAutoExchangeMin;
     const Variant *Vx = nullptr;
+    const int fx = kFormExchange;
     uint32_t Px = 0;
     if (autox) {
         Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u);
-        if (!Vx || !Vx->fn_x)
+        if (!Vx || !Vx->launch[fx])
             return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
-        if ((rc = grid_of(Vx->fn_x(true), Vx->nt, xch_lds_bytes(Vx->tile, R.w), &Px)))
+        if ((rc = grid_of(Vx->fn[fx](true), Vx->nt, Vx->lds[fx], &Px)))
             return rc;
     }
 
@@ -359,6 +362,13 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     uint64_t lo = 0, hi = n;
     uint32_t level = 0;  // global level index (fresh offsets per level)
     ro->levels_run = 0;
+    // Expected region of each level (the model of planned_levels): levels
+    // from the third on launch about three workgroups per expected group
+    // rather than a full grid, so that a small level dispatches, and the next
+    // level reduces, only a few partials (a larger region than expected only
+    // gives each workgroup more groups).
+    const uint64_t tail_group = (uint64_t)s_max_t << log2b_t;
+    double expect = (double)n * 4.4 / std::sqrt((double)((uint64_t)R.s_max << R.log2b));
     for (;;) {
         LevelArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -378,11 +388,17 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
         for (uint32_t k = 0; k < budget; k++, level++) {
             const bool first = k == 0;
             const bool tail = level >= 2;
-            const bool xl = xch || (level >= 1 && xrest);  // this level in the exchange form
-            const Variant *Vl = tail ? Vt : V;
+            const bool xl = xch;  // this level in the exchange form
             a.log2b = tail ? log2b_t : R.log2b;
             a.s_max = tail ? s_max_t : R.s_max;
             uint32_t grid = tail ? Pt : level == 0 ? P : P1;
+            if (tail) {
+                const double want = 3.0 * std::ceil(expect / (double)tail_group) + 8.0;
+                if (want < (double)grid)
+                    grid = (uint32_t)want;
+            }
+            if (level >= 1)
+                expect *= 0.11;  // the region entering the next level
             if (first) {
                 const Geo G = plan_geo(lo, hi, a.log2b, a.s_max);
                 grid = G.g < grid ? G.g : grid;
@@ -395,7 +411,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             a.prev_count = prev_count;
             a.out = ws->part + (size_t)k * 2 * kMaxGrid;
             a.ctl = ws->ctl + (size_t)k * kCtlWords;
-            if (level == 0 && (xch || autox)) {
+            if (level == 0 && xch) {
                 if ((e = launch_xch_prepare(dtype, base, n, pivot, ws->result, xch, st)) != hipSuccess)
                     return fail_device(e, "exchange prepare launch");
                 ro->launches++;
@@ -406,30 +422,35 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             }
             a.written = xl ? ws->result + (level == 0 ? kResultWrittenFirst : kResultWritten) : nullptr;
             // without the sample kernel, the first level clears the count of stored elements
-            a.reset = level == 0 && !xch && !autox && xrest ? ws->result + kResultWritten : nullptr;
             if (level == 0 && autox) {
-                // the pair: stable form (gate 0), then exchange form (gate 1); the
-                // exchange form leaves the stable form's partial slots alone
-                a.gate = ws->result + kResultGate;
+                // the pair: stable form (gate 0, which samples the keys and records
+                // the choice), then exchange form (gate 1); the exchange form
+                // leaves the stable form's partial slots alone
+                a.sample_out = ws->result;
+                a.gate = nullptr;
                 a.gate_want = 0;
                 a.gate_keep = 0;
-                if ((e = launch_stable(first, grid, a, st)) != hipSuccess)
+                if ((e = V->launch[f0](first, grid, a, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 LevelArgs ax = a;
                 ax.s_max = (uint32_t)(Vx->tile / ((uint64_t)R.b * R.w));
                 const Geo Gx = plan_geo(lo, hi, ax.log2b, ax.s_max);
                 const uint32_t grid_x = Gx.g < Px ? Gx.g : Px;
+                ax.sample_out = nullptr;
+                ax.gate = ws->result + kResultGate;
                 ax.gate_want = 1;
                 ax.gate_keep = grid;
                 ax.written = ws->result + kResultWrittenFirst;
-                if ((e = Vx->launch_x(first, grid_x, ax, st)) != hipSuccess)
+                if ((e = Vx->launch[fx](first, grid_x, ax, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 ro->launches += 2;
+                a.sample_out = nullptr;
                 a.gate = nullptr;
                 a.written = nullptr;
                 grid = grid_x > grid ? grid_x : grid;
             } else {
-                if ((e = (xl ? Vl->launch_x : level == 0 ? launch_stable : Vl->launch)(first, grid, a, st)) != hipSuccess)
+                const LevelLaunch L = level == 0 ? V->launch[f0] : tail ? Vt->launch[ft] : V->launch[f1];
+                if ((e = L(first, grid, a, st)) != hipSuccess)
                     return fail_device(e, "level kernel launch");
                 ro->launches++;
                 if (xl && level < 64)

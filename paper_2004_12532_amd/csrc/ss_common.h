@@ -90,8 +90,28 @@ struct LevelArgs {
     uint32_t gate_keep;     //   from workgroup gate_keep on (the other kernel of the pair wrote the rest)
     const uint64_t *gate;   // null: always run
     uint64_t *written;      // exchange form: elements stored, summed over the workgroups (null: not kept)
-    uint64_t *reset;        // first level: workgroup 0 clears this word at the start (null: none)
+    uint64_t *sample_out;   // first level of the automatic choice: take the form from the key sample,
+                            //   run only if it selects gate_want, and (workgroup 0) store the choice and
+                            //   clear the exchange form's counts in these result words (null: no sample)
 };
+
+// The automatic choice's key sample: kGateRuns runs of kGateRunLen
+// consecutive keys, run c starting at c n / kGateRuns.  The exchange form is
+// chosen when at most 1/den of the sample, or at least 1 - 1/den, are
+// predecessors (den = 10 for 16-byte records, 16 otherwise).
+constexpr uint32_t kGateRuns = 64;
+constexpr uint32_t kGateRunLen = 64;
+constexpr uint32_t kGateSamples = kGateRuns * kGateRunLen;
+__host__ __device__ __forceinline__ bool gate_skewed(uint64_t preds, int w)
+{
+    const uint64_t den = w >= 16 ? 10 : 16;
+    return preds * den <= kGateSamples || preds * den >= (den - 1) * kGateSamples;
+}
+
+// Forms of a level kernel's store (ss_level_rs.h): every element stored to
+// its slot from registers, the write-minimal exchange, or the stable
+// partition staged in an LDS tile and written back as whole lines.
+enum { kFormDirect = 0, kFormExchange = 1, kFormStaged = 2, kForms = 3 };
 
 constexpr int kCtlWords = 8;        // words per level record
 constexpr int kResultWordsDev = 8;  // result words ahead of the level records in the host copy

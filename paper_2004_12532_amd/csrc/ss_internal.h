@@ -21,8 +21,6 @@ constexpr uint32_t kDefaultLineBytes = 512;
 constexpr uint32_t kExchangeFlags = SS_FLAG_EXCHANGE | SS_FLAG_EXCHANGE_SKEWED;
 constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a group's slots
 constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
-// LDS of the exchange form's slot table for groups of `tile` bytes of w-byte elements
-inline size_t xch_lds_bytes(uint32_t tile, int w) { return (size_t)tile / (uint32_t)w; }
 constexpr int kResultWrittenFirst = 5;  // result word: elements stored by a first level in the exchange form
 constexpr int kResultWritten = 6;   // result word: elements stored by later exchange-form levels
 constexpr int kResultGate = 7;      // result word: 1 when the exchange form was chosen
@@ -67,37 +65,32 @@ struct RunOut {
     uint32_t level_g[SS_MAX_LEVELS], level_s[SS_MAX_LEVELS];
 };
 
+using LevelLaunch = hipError_t (*)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+using LevelFn = const void *(*)(bool first);
+
+// A level kernel shape: its launchers, kernel handles and dynamic LDS per
+// store form (kForm*; null where the engine has no such form: the LDS
+// engine has only the stable form).
 struct Variant {
     int dtype;
     uint32_t engine;
     uint32_t tile;
     int nt;
-    hipError_t (*launch)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-    const void *(*fn)(bool first);
-    // the write-minimal exchange form (register engines; null for the LDS engine)
-    hipError_t (*launch_x)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-    const void *(*fn_x)(bool first);
-    // the stable form staged in an LDS tile (register engines; null for the LDS engine)
-    hipError_t (*launch_s)(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-    const void *(*fn_s)(bool first);
+    LevelLaunch launch[kForms];
+    LevelFn fn[kForms];
+    size_t lds[kForms];
 };
 
 template <typename T, int NT, int TB>
 hipError_t launch_level(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
 template <typename T, int NT, int TB>
 const void *level_fn(bool first);
-template <typename T, int NT, int NV>
-hipError_t launch_level_rs(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-template <typename T, int NT, int NV>
-const void *level_rs_fn(bool first);
-template <typename T, int NT, int NV>
-hipError_t launch_level_staged(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-template <typename T, int NT, int NV>
-const void *level_staged_fn(bool first);
-template <typename T, int NT, int NV>
-hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
-template <typename T, int NT, int NV>
-const void *level_xch_fn(bool first);
+template <typename T, int NT, int NV, int FORM>
+hipError_t launch_level_rs_t(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st);
+template <typename T, int NT, int NV, int FORM>
+const void *level_rs_fn_t(bool first);
+template <typename T, int NT, int NV, int FORM>
+size_t level_form_lds();
 const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile);
 hipError_t launch_xch_prepare(int dtype, const char *base, uint64_t n, uint64_t pivot, uint64_t *result, bool force,
                               hipStream_t st);

@@ -41,11 +41,7 @@
 
 namespace ss {
 
-// Forms of the step's store: every element stored to its slot from
-// registers, the write-minimal exchange, or the stable partition staged in
-// an LDS tile and written back as whole lines.
-enum { kFormDirect = 0, kFormExchange = 1, kFormStaged = 2 };
-
+// Store forms: kForm* in ss_common.h.
 template <typename T, int NT, int NV, bool FIRST, int FORM>
 __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 {
@@ -63,11 +59,38 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 
     const int tid = threadIdx.x;
     const uint32_t bid = blockIdx.x;
-    if (FIRST && a.reset && bid == 0 && tid == 0)
-        *a.reset = 0ull;
 
     // A first level launched as one of a stable/exchange pair: the kernel the
-    // gate word does not select only leaves neutral partials behind.
+    // choice does not select only leaves neutral partials behind.  The first
+    // kernel of the pair takes the choice from the key sample (every
+    // workgroup reads the same 4096 keys) and records it for the second.
+    if (FIRST && a.sample_out) {
+        __shared__ uint32_t sampled;
+        if (tid == 0)
+            sampled = 0;
+        __syncthreads();
+        uint32_t mine = 0;
+        const T *const A = reinterpret_cast<const T *>(a.base);
+        for (uint32_t k = tid; k < kGateSamples; k += NT) {
+            const uint64_t pos = (uint64_t)(k / kGateRunLen) * a.n / kGateRuns + k % kGateRunLen;
+            mine += key_of(A[pos < a.n ? pos : a.n - 1]) < a.pivot;
+        }
+        atomicAdd(&sampled, mine);
+        __syncthreads();
+        const uint32_t skewed = gate_skewed(sampled, W) ? 1u : 0u;
+        if (bid == 0 && tid == 0) {
+            a.sample_out[kResultGate] = skewed;
+            a.sample_out[kResultWritten] = 0ull;
+            a.sample_out[kResultWrittenFirst] = 0ull;
+        }
+        if (skewed != a.gate_want) {
+            if (tid == 0 && bid >= a.gate_keep) {
+                a.out[2 * bid] = ~0ull;
+                a.out[2 * bid + 1] = 0ull;
+            }
+            return;
+        }
+    }
     if (FIRST && a.gate && *a.gate != a.gate_want) {
         if (tid == 0 && bid >= a.gate_keep) {
             a.out[2 * bid] = ~0ull;
@@ -211,6 +234,12 @@ constexpr size_t level_rs_lds()
     return FORM == kFormExchange ? LevelCtx<T, NT, NV>::XCH_BYTES
            : FORM == kFormStaged ? (size_t)LevelCtx<T, NT, NV>::NVEC * 16
                                  : 0;
+}
+
+template <typename T, int NT, int NV, int FORM>
+size_t level_form_lds()
+{
+    return level_rs_lds<T, NT, NV, FORM>();
 }
 
 template <typename T, int NT, int NV, int FORM>

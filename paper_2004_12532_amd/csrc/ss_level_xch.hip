@@ -7,21 +7,11 @@
 
 namespace ss {
 
-template <typename T, int NT, int NV>
-hipError_t launch_level_xch(bool first, uint32_t grid, const LevelArgs &a, hipStream_t st)
-{
-    return launch_level_rs_t<T, NT, NV, kFormExchange>(first, grid, a, st);
-}
-
-template <typename T, int NT, int NV>
-const void *level_xch_fn(bool first)
-{
-    return level_rs_fn_t<T, NT, NV, kFormExchange>(first);
-}
-
-#define SS_INSTANTIATE_XCH(T, NT, NV)                                                              \
-    template hipError_t launch_level_xch<T, NT, NV>(bool, uint32_t, const LevelArgs &, hipStream_t); \
-    template const void *level_xch_fn<T, NT, NV>(bool);
+#define SS_INSTANTIATE_FORM(T, NT, NV, FORM)                                                                  \
+    template hipError_t launch_level_rs_t<T, NT, NV, FORM>(bool, uint32_t, const LevelArgs &, hipStream_t); \
+    template const void *level_rs_fn_t<T, NT, NV, FORM>(bool);                                              \
+    template size_t level_form_lds<T, NT, NV, FORM>();
+#define SS_INSTANTIATE_XCH(T, NT, NV) SS_INSTANTIATE_FORM(T, NT, NV, kFormExchange)
 
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint32_t)
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint64_t)
@@ -33,30 +23,22 @@ namespace ss {
 
 namespace {
 
-// Sample size and skew threshold of the automatic choice.  A group of S
-// slots has about q (1 - q) S misplaced pairs when a fraction q of the keys
-// are predecessors, so near q = 0 or 1 only a few percent of the lines are
-// written and the exchange form of the first level (with 32 KiB groups)
-// wins; towards the middle the scattered swaps dirty nearly every line and
-// the stable form with 128 KiB groups is faster.  Measured crossovers at
-// 2^30 elements: q between 1/16 and 1/10 for 8-byte keys, above 1/10 for
-// 16-byte records (fewer elements share a line), so the exchange is chosen
-// when the sampled q is at most 1/den or at least 1 - 1/den.
-// The sample is 64 runs of 64 consecutive keys, run c starting at c n / 64:
-// 4096 keys from 64 pages, so one workgroup reads it with coalesced loads
-// and few address translations (16384 keys at scattered positions took
-// 40 us, nearly all of it translation misses).
-constexpr uint32_t kSkewRuns = 64;
-constexpr uint32_t kRunLen = 64;
-constexpr uint32_t kSkewSamples = kSkewRuns * kRunLen;
+// The sample of the automatic choice (kGateRuns runs of kGateRunLen keys,
+// ss_common.h): a skewed pivot leaves only a few percent of the lines to
+// write, and the exchange form of the first level (with 32 KiB groups) wins;
+// towards the middle the scattered swaps dirty nearly every line and the
+// stable form with 128 KiB groups is faster.  Runs cost few address
+// translations: 16384 keys at scattered positions took 40 us, nearly all of
+// it translation misses.  This kernel serves calls that force the exchange
+// form (it only clears the counts then); the automatic choice samples
+// inside the stable first-level kernel.
 constexpr int kPrepNT = 1024;
-constexpr int kPrepPerThread = kSkewSamples / kPrepNT;
+constexpr int kPrepPerThread = kGateSamples / kPrepNT;
 
 template <typename T>
 __global__ void __launch_bounds__(kPrepNT) k_xch_prepare(const T *A, uint64_t n, uint64_t pivot, uint64_t *result,
                                                           uint32_t force)
 {
-    constexpr uint64_t den = sizeof(T) >= 16 ? 10 : 16;
     __shared__ uint32_t total;
     if (threadIdx.x == 0)
         total = 0;
@@ -69,7 +51,7 @@ __global__ void __launch_bounds__(kPrepNT) k_xch_prepare(const T *A, uint64_t n,
 #pragma unroll
         for (int r = 0; r < kPrepPerThread; r++) {
             const uint64_t run = wave + (uint64_t)r * (kPrepNT / 64);
-            const uint64_t pos = run * n / kSkewRuns + lane;
+            const uint64_t pos = run * n / kGateRuns + lane;
             v[r] = A[pos < n ? pos : n - 1];
         }
         uint32_t mine = 0;
@@ -80,8 +62,7 @@ __global__ void __launch_bounds__(kPrepNT) k_xch_prepare(const T *A, uint64_t n,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint64_t c = total;
-        const bool skewed = c * den <= kSkewSamples || c * den >= (den - 1) * kSkewSamples;
+        const bool skewed = gate_skewed(total, (int)sizeof(T));
         result[kResultGate] = force || skewed ? 1ull : 0ull;
         result[kResultWritten] = 0ull;
         result[kResultWrittenFirst] = 0ull;
