@@ -276,6 +276,20 @@ int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, in
                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                          void *stream, ss_stats *stats);
 
+/* One call per array, the per-array counterpart of ss_partition_batched:
+ * array k is d_base[h_offsets[k], h_offsets[k+1]) (elements; host offsets,
+ * non-decreasing, num + 1 of them), partitioned by h_pivots[k] (host) with
+ * the single-array path of ss_partition_ex (its own level chain, planned
+ * from its length, and base case; an array that fits one group is a single
+ * launch), issued back to back on the stream.  d_splits[k] (device)
+ * receives the split relative to the array's start.  Without h_ms the call
+ * does not synchronize.  With h_ms (host, num floats) an event is recorded
+ * after every array and the call waits for the last one: h_ms[k] is the time
+ * from the call's first launch to array k's completion on the stream.
+ * Section 4 (the step), applied once per array. */
+int ss_partition_each(void *d_base, const uint64_t *h_offsets, size_t num, int dtype, const uint64_t *h_pivots,
+                      uint64_t *d_splits, const ss_params *p, void *stream, float *h_ms);
+
 /* Batched partition of disjoint segments of one array: segment k is
  * d_base[h_starts[k], h_starts[k] + h_lens[k]) in elements (host arrays;
  * segments may appear in any order but must not overlap), with pivot

@@ -102,6 +102,7 @@ _lib.ss_partition_batched.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POIN
                                       ctypes.POINTER(Stats)]
 _lib.ss_partition_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp,
                                        ctypes.POINTER(Stats)]
+_lib.ss_partition_each.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp, _vp]
 _lib.ss_median3_pivots.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, _vp]
 _lib.ss_sort_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp]
 _lib.ss_autotune_batched.argtypes = [_int, _vp, ctypes.POINTER(Tuning)]
@@ -227,6 +228,27 @@ def quicksort(t, *, stats: bool = False, stream=None, **kw):
     _check(_lib.ss_quicksort_ex(ptr, n, dt, ctypes.byref(p), _stream(stream), ctypes.byref(st) if stats else None),
            "ss_quicksort_ex")
     return st.as_dict() if stats else None
+
+
+def partition_each(base, offsets, pivots, splits, *, latencies: bool = False, stream=None, **kw):
+    """ss_partition_each: one single-array call per array base[offsets[k]:offsets[k+1]] with pivot
+    pivots[k] (host sequences), issued from C back to back; splits (int64 CUDA tensor of num entries)
+    receives the splits.  With latencies=True it waits and returns each array's completion time in ms
+    after the first launch (numpy float32 array)."""
+    import numpy as np
+
+    ptr, _, dt = _array(base)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    piv = np.ascontiguousarray(np.asarray([int(x) & ((1 << 64) - 1) for x in pivots], dtype=np.uint64))
+    num = off.size - 1
+    p = make_params(**kw)
+    ms = np.zeros(max(num, 1), dtype=np.float32) if latencies else None
+    _check(_lib.ss_partition_each(ptr, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), num, dt,
+                                  piv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  ctypes.c_void_p(splits.data_ptr()), ctypes.byref(p), _stream(stream),
+                                  ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if latencies else None),
+           "ss_partition_each")
+    return ms[:num] if latencies else None
 
 
 def partition_batched(base, offsets, pivots, splits, *, stats: bool = False, stream=None, **kw):

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "ss.h"
 #include "ss_common.h"
@@ -340,8 +341,8 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
 
     // Automatic choice for large arrays: the first level is launched as a
     // pair, the stable form with the default groups and the exchange form
-    // with 32 KiB groups; a one-workgroup sample of the keys sets the gate
-    // word that makes exactly one of them run.
+    // with 32 KiB groups; the stable kernel takes the choice from a sample of
+    // the keys and records it, so that exactly one of them runs.
     const bool autox = R.auto_xch && n >= kAutoExchangeMin;
     const Variant *Vx = nullptr;
     const int fx = kFormExchange;
@@ -358,6 +359,11 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const bool strided = R.algo == SS_STRIDED;
     const bool one_level = (R.flags & SS_FLAG_ONE_LEVEL) != 0;
     const uint32_t budget = one_level || strided ? 1u : R.levels ? R.levels : planned_levels(n, R);
+    // An asynchronous call on a region of one group with a register body is
+    // a single launch: the group's splitting position is the split, which the
+    // first level stores itself (no base case, no host copy).
+    const bool single = !sync && !timing && !one_level && !strided && !xch && !autox && d_split &&
+                        regs != SS_ENGINE_LDS && n <= ((uint64_t)R.s_max << R.log2b);
 
     uint64_t lo = 0, hi = n;
     uint32_t level = 0;  // global level index (fresh offsets per level)
@@ -421,6 +427,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
                     return fail_device(e, "hipEventRecord");
             }
             a.written = xl ? ws->result + (level == 0 ? kResultWrittenFirst : kResultWritten) : nullptr;
+            a.split_out = single ? d_split : nullptr;
             // without the sample kernel, the first level clears the count of stored elements
             if (level == 0 && autox) {
                 // the pair: stable form (gate 0, which samples the keys and records
@@ -465,6 +472,10 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
             prev_count = grid;
         }
         uint64_t *host = sync ? ws->host_dev : nullptr;
+        if (single) {
+            ro->levels_run = level;
+            return SS_OK;
+        }
         if (!one_level) {
             // The serial base case (Recursive Smoothed Striding) or the Serial
             // Cleanup Step (Strided): one workgroup partitions [v_min, v_max).
@@ -721,6 +732,70 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
         *h_split = (size_t)ro.split;
     if (stats)
         fill_stats(stats, ro, R, dtype);
+    return SS_OK;
+}
+
+int ss_partition_each(void *d_base, const uint64_t *h_offsets, size_t num, int dtype, const uint64_t *h_pivots,
+                      uint64_t *d_splits, const ss_params *p, void *stream, float *h_ms)
+{
+    if (num == 0)
+        return SS_OK;
+    if (!h_offsets || !h_pivots || !d_splits)
+        return fail_msg(SS_EINVAL, "null offsets, pivots or splits");
+    if ((uintptr_t)d_splits % 8)
+        return fail_msg(SS_EINVAL, "d_splits not 8-byte aligned");
+    for (size_t k = 0; k < num; k++)
+        if (h_offsets[k + 1] < h_offsets[k])
+            return fail_msg(SS_EINVAL, "offsets must not decrease");
+    int rc = check_array(d_base, (size_t)h_offsets[num], dtype);
+    if (rc)
+        return rc;
+    Resolved R;
+    rc = resolve_params(p, dtype, &R, SS_ENGINE_STAGED);
+    if (rc)
+        return rc;
+    if (R.algo != SS_SMOOTHED && R.algo != SS_STRIDED)
+        return fail_msg(SS_EINVAL, "ss_partition_each runs Smoothed Striding or Strided");
+    if ((rc = check_lines(h_offsets[num], R)))
+        return rc;
+    R.flags &= ~SS_FLAG_TIME;
+    hipStream_t st = (hipStream_t)stream;
+    const int w = elem_size(dtype);
+    static thread_local std::vector<hipEvent_t> evs;
+    if (h_ms) {
+        while (evs.size() < num + 1) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess)
+                return fail_msg(SS_EDEVICE, "hipEventCreate");
+            evs.push_back(e);
+        }
+        if (hipEventRecord(evs[0], st) != hipSuccess)
+            return fail_msg(SS_EDEVICE, "hipEventRecord");
+    }
+    for (size_t k = 0; k < num; k++) {
+        const uint64_t n = h_offsets[k + 1] - h_offsets[k];
+        if (n == 0) {
+            const hipError_t e = hipMemsetAsync(d_splits + k, 0, sizeof(uint64_t), st);
+            if (e != hipSuccess)
+                return fail_device(e, "hipMemsetAsync");
+        } else {
+            RunOut ro;
+            std::memset(&ro, 0, sizeof(ro));
+            if ((rc = run_partition((char *)d_base + h_offsets[k] * (uint64_t)w, (size_t)n, dtype, h_pivots[k], R, st,
+                                    d_splits + k, false, &ro)))
+                return rc;
+        }
+        if (h_ms && hipEventRecord(evs[k + 1], st) != hipSuccess)
+            return fail_msg(SS_EDEVICE, "hipEventRecord");
+    }
+    if (h_ms) {
+        hipError_t e = hipEventSynchronize(evs[num]);
+        if (e != hipSuccess)
+            return fail_device(e, "hipEventSynchronize");
+        for (size_t k = 0; k < num; k++)
+            if ((e = hipEventElapsedTime(&h_ms[k], evs[0], evs[k + 1])) != hipSuccess)
+                return fail_device(e, "hipEventElapsedTime");
+    }
     return SS_OK;
 }
 

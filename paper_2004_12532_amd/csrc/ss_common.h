@@ -90,6 +90,8 @@ struct LevelArgs {
     uint32_t gate_keep;     //   from workgroup gate_keep on (the other kernel of the pair wrote the rest)
     const uint64_t *gate;   // null: always run
     uint64_t *written;      // exchange form: elements stored, summed over the workgroups (null: not kept)
+    uint64_t *split_out;    // first level of a region of one group: workgroup 0 stores the split here
+                            //   (null: a later kernel does)
     uint64_t *sample_out;   // first level of the automatic choice: take the form from the key sample,
                             //   run only if it selects gate_want, and (workgroup 0) store the choice and
                             //   clear the exchange form's counts in these result words (null: no sample)

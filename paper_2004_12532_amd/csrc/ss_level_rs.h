@@ -214,6 +214,8 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
     if (tid == 0) {
         a.out[2 * bid] = vmin;
         a.out[2 * bid + 1] = vmax;
+        if (FIRST && a.split_out && bid == 0 && G.g == 1)
+            *a.split_out = vmin;  // one group: its splitting position is the split
         if (XCH && a.written && written)
             atomicAdd(reinterpret_cast<unsigned long long *>(a.written), (unsigned long long)written);
     }

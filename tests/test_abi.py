@@ -64,6 +64,22 @@ def test_argument_validation_without_device():
                              ctypes.byref(split), None) == -1
     assert split.value == 7  # untouched on argument errors
     assert L.ss_quicksort(None, 5, ss.SS_U32) == -1
+    # the per-array loop: null or decreasing offsets, null pivots or splits
+    off = (ctypes.c_uint64 * 3)(0, 8, 4)
+    piv = (ctypes.c_uint64 * 2)(1, 2)
+    p = ss.make_params()
+    each = L.ss_partition_each
+    assert each(ctypes.c_void_p(0x1000), None, 2, ss.SS_U64, piv, ctypes.c_void_p(0x2000), ctypes.byref(p), None,
+                None) == -1
+    assert each(ctypes.c_void_p(0x1000), off, 2, ss.SS_U64, piv, ctypes.c_void_p(0x2000), ctypes.byref(p), None,
+                None) == -1
+    off[2] = 12
+    assert each(ctypes.c_void_p(0x1000), off, 2, ss.SS_U64, None, ctypes.c_void_p(0x2000), ctypes.byref(p), None,
+                None) == -1
+    assert each(ctypes.c_void_p(0x1000), off, 2, ss.SS_U64, piv, None, ctypes.byref(p), None, None) == -1
+    assert each(ctypes.c_void_p(0x1000), off, 2, ss.SS_U64, piv, ctypes.c_void_p(0x2004), ctypes.byref(p), None,
+                None) == -1
+    assert each(ctypes.c_void_p(0x1000), off, 0, ss.SS_U64, piv, None, ctypes.byref(p), None, None) == 0  # nothing
 
 
 def test_strerror_and_aux_bytes():

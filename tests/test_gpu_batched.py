@@ -229,3 +229,36 @@ def test_batched_lds_engine_parity(ss, kind, tile):
     _check(data, out, offsets, pivots, splits)
     out_r, splits_r, _ = _run_batched(ss, data, offsets, pivots, engine="regs", tile_bytes=tile)
     assert np.array_equal(splits, splits_r) and np.array_equal(out, out_r)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64", "kv"])
+def test_partition_each_matches_oracle_and_single_calls(ss, kind):
+    """The per-array loop issued from C: every array's split and sides equal the
+    oracle's, and its bytes equal a separate single-array call's (arrays that fit
+    one group take the single-launch path, longer ones the planned chain)."""
+    import torch
+    lengths = np.concatenate([[0, 1, 2, 63, 64, 65, 4095, 16384, 16385, 70001],
+                              workloads.lognormal_lengths(120, 19, median_log2=12.0, sigma_log2=1.5, lo=1,
+                                                          hi=1 << 19),
+                              [1 << 20, 7]]).astype(np.int64)
+    data, offsets, pivots = _batch(kind, lengths, 13)
+    t = to_device(data)
+    sp = torch.full((len(pivots),), -7, dtype=torch.int64, device="cuda")
+    lat = ss.partition_each(t, offsets, [int(x) for x in pivots], sp, latencies=True)
+    out = to_host(t, data)
+    splits = sp.cpu().numpy().view(np.uint64)
+    _check(data, out, offsets, pivots, splits)
+    assert lat.shape == (len(pivots),) and np.all(np.diff(lat) >= 0) and lat[-1] > 0
+    for k in (0, 3, 7, 9, len(pivots) - 2):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        one = to_device(data[a:b].copy())
+        s1 = ss.partition(one, int(pivots[k])) if b > a else 0
+        assert s1 == int(splits[k])
+        assert np.array_equal(to_host(one, data[a:b]), out[a:b]), k
+    # without latencies the call does not synchronize; the splits land on the stream
+    t2 = to_device(data)
+    sp2 = torch.full((len(pivots),), -7, dtype=torch.int64, device="cuda")
+    ss.partition_each(t2, offsets, [int(x) for x in pivots], sp2)
+    torch.cuda.synchronize()
+    assert np.array_equal(sp2.cpu().numpy().view(np.uint64), splits)
+    assert np.array_equal(to_host(t2, data), out)
