@@ -276,6 +276,22 @@ int ss_partition_batched(void *d_base, const uint64_t *h_offsets, size_t num, in
                          const uint64_t *d_pivots, uint64_t *d_splits, const ss_params *p,
                          void *stream, ss_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the
+ * asynchronous form of ss_partition_ex (d_split required, no h_split or
+ * stats) that allocates nothing.  Its partials, level records and result
+ * words live in one fixed device array per GPU (16 level slots, about
+ * 1 MiB; the library holds it until the process ends) instead of the
+ * per-stream workspace.  p may be NULL; it accepts Smoothed Striding or
+ * Strided, any b, tile_bytes and engine, SS_FLAG_STABLE / SS_FLAG_EXCHANGE*,
+ * and max_levels up to 16 (SS_EINVAL above; the default plan stays far
+ * below).  SS_FLAG_TIME and SS_FLAG_GRAPH are rejected.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialized by the caller.  The same
+ * arrangement and split as ss_partition_ex with the same parameters. */
+int ss_partition_noalloc(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_params *p, void *stream,
+                         uint64_t *d_split);
+
 /* One call per array, the per-array counterpart of ss_partition_batched:
  * array k is d_base[h_offsets[k], h_offsets[k+1]) (elements; host offsets,
  * non-decreasing, num + 1 of them), partitioned by h_pivots[k] (host) with

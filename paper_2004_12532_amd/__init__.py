@@ -103,6 +103,7 @@ _lib.ss_partition_batched.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POIN
 _lib.ss_partition_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp,
                                        ctypes.POINTER(Stats)]
 _lib.ss_partition_each.argtypes = [_vp, _vp, _sz, _int, _vp, _vp, ctypes.POINTER(Params), _vp, _vp]
+_lib.ss_partition_noalloc.argtypes = [_vp, _sz, _int, _u64, ctypes.POINTER(Params), _vp, _vp]
 _lib.ss_median3_pivots.argtypes = [_vp, _vp, _vp, _sz, _int, _vp, _vp, _vp]
 _lib.ss_sort_segments.argtypes = [_vp, _vp, _vp, _sz, _int, _vp]
 _lib.ss_autotune_batched.argtypes = [_int, _vp, ctypes.POINTER(Tuning)]
@@ -210,6 +211,15 @@ def partition_async(t, pivot: int, d_split, *, stream=None, **kw) -> None:
     p = make_params(**kw)
     _check(_lib.ss_partition_ex(ptr, n, dt, pivot & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
                                 ctypes.c_void_p(d_split.data_ptr()), None, None), "ss_partition_ex")
+
+
+def partition_noalloc(t, pivot: int, d_split, *, stream=None, **kw) -> None:
+    """ss_partition_noalloc: asynchronous partition that allocates no device memory; the split lands
+    in d_split[0] (an int64 CUDA tensor)."""
+    ptr, n, dt = _array(t)
+    p = make_params(**kw)
+    _check(_lib.ss_partition_noalloc(ptr, n, dt, pivot & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
+                                     ctypes.c_void_p(d_split.data_ptr())), "ss_partition_noalloc")
 
 
 def partition_plain(t, pivot: int) -> int:

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ss_level.hip", "ss_level_rs.hip", "ss_level_xch.hip", "ss_strided.hip", "ss_lowspace.hip",
-           "ss_quicksort.hip", "ss_batched.hip", "ss_serving.hip", "ss_probe.hip", "ss_api.cpp"]
+           "ss_quicksort.hip", "ss_batched.hip", "ss_serving.hip", "ss_probe.hip", "ss_noalloc.hip", "ss_api.cpp"]
 
 FLAGS = [
     "--offload-arch=" + ARCH,

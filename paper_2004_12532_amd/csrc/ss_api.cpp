@@ -280,10 +280,11 @@ uint32_t planned_levels(uint64_t n, const Resolved &R)
 
 // Run the recursion of Smoothed Striding (or the single Strided step) on
 // [lo0, hi0) of the array.  Writes the result record to ws->result and the
-// split to d_split.  When `sync` the host finishes the recursion if the
-// device budget runs out and fills *host_out.
+// split to d_split.  When `sync` it waits and fills *ro from the host copy.
+// `wsx` (nullable) replaces the per-(device, stream) workspace: a workspace
+// without host memory or events, for asynchronous calls only.
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
-                  uint64_t *d_split, bool sync, RunOut *ro)
+                  uint64_t *d_split, bool sync, RunOut *ro, Workspace *wsx)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -293,10 +294,11 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     int rc = device_info(dev, &cus, &lds);
     if (rc)
         return rc;
-    Workspace *ws = nullptr;
-    rc = get_workspace(dev, st, &ws);
-    if (rc)
+    Workspace *ws = wsx;
+    if (!ws && (rc = get_workspace(dev, st, &ws)))
         return rc;
+    if (wsx && (sync || (R.flags & SS_FLAG_TIME)))
+        return fail_msg(SS_EINVAL, "a caller-supplied workspace serves asynchronous calls only");
     auto grid_of = [&](const void *fn, int nt, size_t shmem, uint32_t *grid) -> int {
         int occ = 0;
         const int r = occupancy(dev, fn, nt, &occ, shmem);
@@ -359,6 +361,8 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const bool strided = R.algo == SS_STRIDED;
     const bool one_level = (R.flags & SS_FLAG_ONE_LEVEL) != 0;
     const uint32_t budget = one_level || strided ? 1u : R.levels ? R.levels : planned_levels(n, R);
+    if (budget > ws->levels_cap)
+        return fail_msg(SS_EINVAL, "more levels than the workspace holds");
     // An asynchronous call on a region of one group with a register body is
     // a single launch: the group's splitting position is the split, which the
     // first level stores itself (no base case, no host copy).
@@ -599,7 +603,7 @@ static int hybrid_partition(char *base, size_t n, int dtype, uint64_t pivot, con
             return fail_msg(SS_EDEVICE, "hipEventCreate");
         (void)hipEventRecord(t0, st);
     }
-    int rc = run_partition(base, n, dtype, pivot, R1, st, nullptr, true, &ro);
+    int rc = run_partition(base, n, dtype, pivot, R1, st, nullptr, true, &ro, nullptr);
     if (rc)
         return rc;
     uint64_t split = ro.vmin;
@@ -716,7 +720,7 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
             return fail_msg(SS_EDEVICE, "hipEventCreate");
         (void)hipEventRecord(t0, st);
     }
-    rc = run_partition((char *)d_ptr, n, dtype, pivot, R, st, d_split, sync || timing, &ro);
+    rc = run_partition((char *)d_ptr, n, dtype, pivot, R, st, d_split, sync || timing, &ro, nullptr);
     if (timing) {
         (void)hipEventRecord(t1, st);
         (void)hipEventSynchronize(t1);
@@ -782,7 +786,7 @@ int ss_partition_each(void *d_base, const uint64_t *h_offsets, size_t num, int d
             RunOut ro;
             std::memset(&ro, 0, sizeof(ro));
             if ((rc = run_partition((char *)d_base + h_offsets[k] * (uint64_t)w, (size_t)n, dtype, h_pivots[k], R, st,
-                                    d_splits + k, false, &ro)))
+                                    d_splits + k, false, &ro, nullptr)))
                 return rc;
         }
         if (h_ms && hipEventRecord(evs[k + 1], st) != hipSuccess)

@@ -33,6 +33,7 @@ struct Workspace {
     uint64_t *host_dev = nullptr;  // the same memory as seen from the device
     size_t part_words = 0, ctl_words = 0;
     size_t bytes = 0;
+    uint32_t levels_cap = kMaxLevels;  // level slots of part and ctl
     hipEvent_t ev[4] = {};
 };
 
@@ -113,7 +114,7 @@ int occupancy(int dev, const void *fn, int nt, int *blocks, size_t shmem = 0);
 int get_workspace(int dev, void *stream, Workspace **out);
 void fill_stats(ss_stats *st, const RunOut &ro, const Resolved &R, int dtype);
 int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolved &R, hipStream_t st,
-                  uint64_t *d_split, bool sync, RunOut *ro);
+                  uint64_t *d_split, bool sync, RunOut *ro, Workspace *wsx);
 uint32_t planned_levels(uint64_t n, const Resolved &R);
 
 // Size classes of a batched call: arrays of length <= max_len[c] (and above
