@@ -322,7 +322,7 @@ def run_quicksort(args, distinct):
             "partition_levels": stats[0]["levels"], "sorted": ok,
             "effective_GBps_per_level": round(2 * n * 4 * stats[0]["levels"] / (wall / steps) / 1e9, 1),
             "config": {"workload": "quicksort_u32_2p28" + ("_d%d" % distinct if distinct else ""), "n": n,
-                       "leaf": 1 << 14, "pivot": "median of 3"},
+                       "leaf": 1 << 14, "pivot": "median of 64 sampled keys"},
             "cpu_baseline": {"value": round(m / tc, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
                              "sample": "serial quicksort of 2^24 keys of the same generator, %.3f s" % tc}}
 

@@ -242,9 +242,11 @@ int ss_partition_ex(void *d_ptr, size_t n, int dtype, uint64_t pivot, const ss_p
 
 /* Sort d_ptr[0, n) ascending by key in place with a parallel quicksort built
  * on the partition (Section 5.2, "Example Application: A Full Quicksort"):
- * median-of-3 pivots, the partition at every level for all segments longer
- * than 2^14 elements, equal keys gathered in a final middle block, and a
- * workgroup-local sort in LDS for the short segments.  SS_KV16 payloads move
+ * every segment's pivot is the lower median of 64 of its keys at equally
+ * spaced positions, the partition runs at every level for all segments
+ * longer than 2^14 elements (8192 for SS_KV16), equal keys are gathered in a
+ * final middle block, and a workgroup-local sort in LDS finishes the short
+ * segments.  SS_KV16 payloads move
  * with their keys; the order of records with equal keys is unspecified.
  * Blocking (default stream). */
 int ss_quicksort(void *d_ptr, size_t n, int dtype);
@@ -393,15 +395,21 @@ int ss_server_status(ss_server *s, uint32_t *flags);
  * what admission adds to the job's input bytes. */
 size_t ss_server_job_aux_bytes(int dtype, int kind, uint64_t len);
 
-/* The quicksort's median-of-3 pivot of every segment (Section 5.2 quicksort;
- * the median of the keys at offsets 0, len/2 and len-1): d_pivots[k]
+/* Median-of-3 pivot of every segment (a classic quicksort pivot rule for
+ * callers that drive their own quicksort levels, Section 5.2; ss_quicksort
+ * itself uses a 64-key sample median): the median of the keys at offsets 0,
+ * len/2 and len-1, into d_pivots[k]
  * (device) and, if h_pivots != NULL, h_pivots[k] (host, call synchronizes).
  * Segment lengths must be >= 1. */
 int ss_median3_pivots(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
                       uint64_t *d_pivots, uint64_t *h_pivots, void *stream);
 
 /* Sort every segment ascending by key in place with the quicksort's
- * workgroup-local LDS sort (stable radix sort; one workgroup per segment).
+ * workgroup-local LDS sort, one workgroup per segment: SS_U32 and SS_U64
+ * keys are bucketed by their offset from the segment's smallest key and the
+ * buckets finished by insertion (a radix sort when a bucket is crowded);
+ * SS_KV16 records take a stable radix sort, so records with equal keys keep
+ * their order.
  * Segment lengths must be in [1, ss_sort_segment_cap(dtype)]. */
 int ss_sort_segments(void *d_base, const uint64_t *h_starts, const uint64_t *h_lens, size_t num, int dtype,
                      void *stream);

@@ -67,11 +67,18 @@ __device__ __forceinline__ uint32_t bnum(const BatchState &B)
     return B.count ? *B.count : B.num;
 }
 
+// Element at which array k's line grid starts.
+__device__ __forceinline__ uint64_t line_origin(const BatchState &B, uint32_t k)
+{
+    return B.base_lines ? 0ull : B.start[k];
+}
+
 __device__ __forceinline__ uint32_t plan_groups(const BatchState &B, const BatchGeom &Gm, uint32_t k, uint64_t lo,
                                                 uint64_t hi)
 {
     const uint32_t c = B.cls[k];
-    return plan_geo(lo - B.start[k], hi - B.start[k], Gm.C.log2b[c], Gm.C.s_max[c]).g;
+    const uint64_t o = line_origin(B, k);
+    return plan_geo(lo - o, hi - o, Gm.C.log2b[c], Gm.C.s_max[c]).g;
 }
 
 // First level: every array's region is the whole array.
@@ -267,7 +274,7 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
             k = B.imap[t];
         }
         const uint32_t i = (uint32_t)(t - B.first[k]);
-        const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
+        const uint64_t lo = B.lo[k], hi = B.hi[k], start = line_origin(B, k);
         const uint32_t cl = B.cls[k], log2b = Gm.C.log2b[cl];
         const Geo G = plan_geo(lo - start, hi - start, log2b, Gm.C.s_max[cl]);
         Ctx x;
@@ -275,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_blevel(BatchState B, BatchGeom Gm)
         x.s = G.s;
         x.fp = G.fp;
         x.real_end = (uint64_t)G.fp + (hi - lo);
-        x.A0 = Gm.base + (lo - G.fp) * W;  // line grid counted from the array's first element
+        x.A0 = Gm.base + (lo - G.fp) * W;  // line grid counted from the array's line origin
         x.log2b = log2b;
         x.vpl_log2 = log2b + Ctx::LOG2W - 4;
         x.nvec = G.s << x.vpl_log2;
@@ -351,7 +358,7 @@ __global__ void __launch_bounds__(NT, 4) k_blevel_lds(BatchState B, BatchGeom Gm
             k = B.imap[t];
         }
         const uint32_t i = (uint32_t)(t - B.first[k]);
-        const uint64_t lo = B.lo[k], hi = B.hi[k], start = B.start[k];
+        const uint64_t lo = B.lo[k], hi = B.hi[k], start = line_origin(B, k);
         const uint32_t cl = B.cls[k], log2b = Gm.C.log2b[cl];
         const Geo G = plan_geo(lo - start, hi - start, log2b, Gm.C.s_max[cl]);
         Ctx x;
@@ -403,15 +410,16 @@ __global__ void __launch_bounds__(NT, 4) k_blevel_lds(BatchState B, BatchGeom Gm
 
 // Arrays still open after the last level: one workgroup each partitions the
 // remaining region serially (block two-pointer exchange).
+// 32 KiB blocks per serial step, as in the single-array cleanup.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_bcleanup(BatchState B, BatchGeom Gm)
 {
-    __shared__ CleanupSmem<T, 1024, 16384> S;
+    __shared__ CleanupSmem<T, 1024, 32768> S;
     const uint32_t num = bnum(B);
     for (uint32_t k = blockIdx.x; k < num; k += gridDim.x) {
         if (B.split[k] != ~0ull)
             continue;
-        const uint64_t sp = cleanup_region<T, 1024, 16384>(reinterpret_cast<T *>(Gm.base), B.pivot[k], B.lo[k],
+        const uint64_t sp = cleanup_region<T, 1024, 32768>(reinterpret_cast<T *>(Gm.base), B.pivot[k], B.lo[k],
                                                             B.hi[k], S);
         if (threadIdx.x == 0)
             B.split[k] = sp;

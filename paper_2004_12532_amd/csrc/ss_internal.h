@@ -143,6 +143,9 @@ struct BatchState {
     uint8_t *cls;      // size class of array k
     const uint32_t *count;  // device word holding the number of arrays (nullable: then num)
     uint32_t num;      // number of arrays, or the capacity when count is set (sizes the grids)
+    uint32_t base_lines = 0;  // 1: lines are counted from the base's element 0 (the arrays are parts of
+                              // one array); 0: from each array's first element (an array gets
+                              // the same bytes alone or in any batch)
 };
 int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, BatchState *B, uint64_t **host_stage,
                   hipEvent_t *stage_copied);

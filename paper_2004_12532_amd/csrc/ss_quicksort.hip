@@ -9,8 +9,8 @@
 //
 // The segment lists live on the device and a level is a fixed chain of
 // launches, so the host never waits for a level before issuing the next one:
-//   * k_qprep: the pivot of every segment -- the median of the keys at its
-//     first, middle and last positions, or the pivot carried over for a
+//   * k_qprep: the pivot of every segment -- the lower median of 64 keys at
+//     equally spaced positions (ss_pivot.h), or the pivot carried over for a
 //     second pass (below);
 //   * the batched partition (ss_batched.hip) by key < pivot;
 //   * k_qchildren: a segment with no key below its pivot p (p is its
@@ -32,7 +32,10 @@
 #include "ss_device.h"
 #include "ss_internal.h"
 #include "ss_leafsort.h"
+#include "ss_pivot.h"
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -79,7 +82,7 @@ struct QLeafArgs {
 };
 
 template <typename T, int CAP, int KEYBITS>
-__global__ void __launch_bounds__(1024) k_qleaf(QLeafArgs a)
+__global__ void __launch_bounds__(kLeafNT) k_qleaf(QLeafArgs a)
 {
     if (a.pub_dst && blockIdx.x == 0 && threadIdx.x == 0) {
         a.pub_dst[0] = *a.pub_count;
@@ -171,7 +174,7 @@ int qleaf_grid(int dtype)
         const void *fn = dtype == SS_U32   ? reinterpret_cast<const void *>(&k_qleaf<uint32_t, 16384, 32>)
                          : dtype == SS_U64 ? reinterpret_cast<const void *>(&k_qleaf<uint64_t, 16384, 64>)
                                            : reinterpret_cast<const void *>(&k_qleaf<KV, 8192, 64>);
-        if (occupancy(dev, fn, 1024, &occ) != SS_OK)
+        if (occupancy(dev, fn, kLeafNT, &occ) != SS_OK)
             return 256;
         g = occ * cus;
     }
@@ -184,16 +187,16 @@ hipError_t launch_qleaf(int dtype, const QLeafArgs &a, hipStream_t st)
     if (!a.count && a.nleaves < grid)
         grid = a.nleaves ? a.nleaves : 1u;
     switch (dtype) {
-    case SS_U32: hipLaunchKernelGGL((k_qleaf<uint32_t, 16384, 32>), dim3(grid), dim3(1024), 0, st, a); break;
-    case SS_U64: hipLaunchKernelGGL((k_qleaf<uint64_t, 16384, 64>), dim3(grid), dim3(1024), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_qleaf<KV, 8192, 64>), dim3(grid), dim3(1024), 0, st, a); break;
+    case SS_U32: hipLaunchKernelGGL((k_qleaf<uint32_t, 16384, 32>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
+    case SS_U64: hipLaunchKernelGGL((k_qleaf<uint64_t, 16384, 64>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_qleaf<KV, 8192, 64>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
     }
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ device-driven levels
 
-// Segment lists: start, len and carried pivot (0: choose the median of 3;
+// Segment lists: start, len and carried pivot (0: choose the sample median;
 // otherwise the pivot of a key <= p pass, stored as p + 1).
 struct SegList {
     uint64_t *start, *len, *pv;
@@ -221,11 +224,14 @@ __global__ void k_qinit(SegList L, QsCtl C, uint64_t n)
     }
 }
 
+// One wavefront per segment (grid: one block of four wavefronts per four
+// segments of the list's capacity).
 template <typename T>
 __global__ void __launch_bounds__(256) k_qprep(const char *base, SegList cur, SegList nxt, QsCtl C)
 {
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k == 0) {
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         *nxt.count = 0;
         *C.leaf_count = 0;
         C.report[1] = 0;
@@ -233,20 +239,13 @@ __global__ void __launch_bounds__(256) k_qprep(const char *base, SegList cur, Se
     if (k >= *cur.count)
         return;
     if (cur.pv[k]) {
-        C.piv[k] = cur.pv[k];
+        if (lane == 0)
+            C.piv[k] = cur.pv[k];
         return;
     }
-    const T *A = reinterpret_cast<const T *>(base) + cur.start[k];
-    const uint64_t l = cur.len[k];
-    uint64_t a = qkey(A[0]), b = qkey(A[l / 2]), c = qkey(A[l - 1]);
-    if (a > b) {
-        const uint64_t t = a;
-        a = b;
-        b = t;
-    }
-    if (b > c)
-        b = c;
-    C.piv[k] = a > b ? a : b;  // median of the three
+    const uint64_t p = sample_median64(reinterpret_cast<const T *>(base) + cur.start[k], cur.len[k], lane);
+    if (lane == 0)
+        C.piv[k] = p;
 }
 
 __device__ __forceinline__ void q_emit(const SegList &nxt, const QsCtl &C, uint64_t s, uint64_t l, uint64_t pv)
@@ -299,6 +298,29 @@ __global__ void __launch_bounds__(256) k_qchildren(SegList cur, SegList nxt, QsC
 }  // namespace
 
 uint64_t quicksort_leaf_cap(int dtype) { return dtype == SS_KV16 ? 8192 : 16384; }
+
+// Partition sublevels of one quicksort level whose longest segment has
+// max_len elements, for groups of S0 elements.  The first sublevel leaves a
+// middle region of about 4.4 / sqrt(S0) of a segment and every later one
+// about 0.11 of the region before it (Section 4's bound on the splitting
+// positions' spread); sublevels are added until the expected region is at
+// most kQsCleanupBytes, which the batched chain's closing one-workgroup
+// cleanup then partitions serially.
+constexpr uint64_t kQsCleanupBytes = 256 << 10;
+
+static uint32_t qs_sublevels(uint64_t max_len, uint64_t S0, int w)
+{
+    if (max_len <= S0)
+        return 1;
+    const double base = (double)kQsCleanupBytes / w;
+    double r = (double)max_len * 4.4 / std::sqrt((double)S0);
+    uint32_t lv = 1;
+    while (r > base && lv < 16) {
+        r *= 0.11;
+        lv++;
+    }
+    return lv;
+}
 
 namespace {
 
@@ -353,7 +375,7 @@ template <typename T>
 hipError_t launch_qprep(const char *base, const SegList &cur, const SegList &nxt, const QsCtl &C, uint32_t grid,
                         hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qprep<T>, dim3(grid), dim3(256), 0, st, base, cur, nxt, C);
+    hipLaunchKernelGGL(k_qprep<T>, dim3(grid), dim3(256), 0, st, base, cur, nxt, C);  // grid: segments / 4
     return hipGetLastError();
 }
 
@@ -415,8 +437,8 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     B.cls = reinterpret_cast<uint8_t *>(take(capS / 8 + 1));
     B.ctl = take(8);
     B.num = (uint32_t)capS;
+    B.base_lines = 1;  // segments are parts of the array: lines stay aligned to the base
 
-    const uint32_t grid_s = (uint32_t)((capS + 255) / 256);
     const BatchClasses BC = batched_default_classes(R);
     hipLaunchKernelGGL(k_qinit, dim3(1), dim3(64), 0, st, LA, C, (uint64_t)n);
     (*launches)++;
@@ -430,22 +452,28 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
             return fail_device(e, "hipStreamSynchronize");
         return SS_OK;
     }
-    auto enqueue = [&](uint32_t L, uint64_t max_len) -> int {
+    // A level's segments are at most twice as many as its parent level's
+    // (and within the list's capacity): the per-segment grids and the batched
+    // state's count bound are sized for that.
+    auto enqueue = [&](uint32_t L, uint64_t max_len, uint64_t max_segs) -> int {
         const SegList &cur = (L & 1) ? LB : LA;
         const SegList &nxt = (L & 1) ? LA : LB;
+        const uint32_t segs = (uint32_t)std::min<uint64_t>(max_segs, capS);
+        const uint32_t grid_s = (segs + 255) / 256, grid_w = (segs + 3) / 4;
         hipError_t e2;
         switch (dtype) {
-        case SS_U32: e2 = launch_qprep<uint32_t>(base, cur, nxt, C, grid_s, st); break;
-        case SS_U64: e2 = launch_qprep<uint64_t>(base, cur, nxt, C, grid_s, st); break;
-        default: e2 = launch_qprep<KV>(base, cur, nxt, C, grid_s, st); break;
+        case SS_U32: e2 = launch_qprep<uint32_t>(base, cur, nxt, C, grid_w, st); break;
+        case SS_U64: e2 = launch_qprep<uint64_t>(base, cur, nxt, C, grid_w, st); break;
+        default: e2 = launch_qprep<KV>(base, cur, nxt, C, grid_w, st); break;
         }
         if (e2 != hipSuccess)
             return fail_device(e2, "pivot launch");
         B.start = cur.start;
         B.len = cur.len;
         B.count = cur.count;
+        B.num = segs;
         const int rc2 =
-            batched_core(base, dtype, R, BC, B, batched_levels(max_len, tile_elems), st, nullptr, launches);
+            batched_core(base, dtype, R, BC, B, qs_sublevels(max_len, tile_elems, R.w), st, nullptr, launches);
         if (rc2)
             return rc2;
         hipLaunchKernelGGL(k_qchildren, dim3(grid_s), dim3(256), 0, st, cur, nxt, C, (const uint64_t *)B.split);
@@ -460,19 +488,19 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     // Level L + 2 is issued once level L has completed: its segments are
     // children of level L + 1's, whose count and longest length level L
     // reported.
-    if ((rc = enqueue(0, n)) || (rc = enqueue(1, n)))
+    if ((rc = enqueue(0, n, 1)) || (rc = enqueue(1, n, 2)))
         return rc;
     uint32_t L = 0;
     for (;;) {
         if ((e = hipEventSynchronize(W->ev[L & 3])) != hipSuccess)
             return fail_device(e, "hipEventSynchronize");
         const volatile uint64_t *rep = W->rep + 2 * L;
-        const uint64_t next_segs = rep[0], next_max = rep[1];
+        const uint64_t next_segs = rep[0], next_max = rep[1];  // level L + 1
         if (next_segs == 0)
             break;  // level L + 1 (already issued) has nothing to do
         if (L + 2 >= kMaxQsLevels)
             return fail_msg(SS_EDEVICE, "quicksort: no progress");
-        if ((rc = enqueue(L + 2, next_max)))
+        if ((rc = enqueue(L + 2, next_max, 2 * next_segs)))
             return rc;
         L++;
     }

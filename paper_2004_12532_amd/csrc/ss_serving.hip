@@ -9,7 +9,8 @@
 // stream with no host decision in between:
 //   k_ssubmit  append the jobs submitted since the last tick to the list;
 //   k_sprep    pivots: a partition job's own pivot, a sort segment's
-//              median-of-3, or the pivot carried over for a key <= p pass;
+//              sample median (ss_pivot.h), or the pivot carried over for a
+//              key <= p pass;
 //   the batched partition of every listed segment (ss_batched.hip);
 //   k_schild   a partition job is done; a sort segment's children go to the
 //              next list (longer than the leaf capacity) or to the leaf list,
@@ -26,6 +27,7 @@
 #include "ss_device.h"
 #include "ss_internal.h"
 #include "ss_leafsort.h"
+#include "ss_pivot.h"
 
 #include <cstring>
 #include <vector>
@@ -97,36 +99,28 @@ __global__ void __launch_bounds__(256) k_ssubmit(SrvDev D, const SrvSub *sub, ui
     D.job[cur][k] = x.slot;
 }
 
+// One wavefront per listed segment (grid: one block per four list entries).
 template <typename T>
 __global__ void __launch_bounds__(256) k_sprep(const char *base, SrvDev D, uint32_t cur)
 {
-    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k == 0) {
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         D.count[cur ^ 1u] = 0;
         D.count[2] = 0;
     }
     if (k >= D.count[cur])
         return;
     const uint32_t slot = D.job[cur][k];
-    if (D.kind[slot] == 0) {
-        D.piv[k] = D.jpivot[slot];
-        return;
-    }
-    if (D.pv[cur][k]) {
-        D.piv[k] = D.pv[cur][k];
-        return;
-    }
-    const T *A = reinterpret_cast<const T *>(base) + D.start[cur][k];
-    const uint64_t l = D.len[cur][k];
-    uint64_t a = qkey(A[0]), b = qkey(A[l / 2]), c = qkey(A[l - 1]);
-    if (a > b) {
-        const uint64_t t = a;
-        a = b;
-        b = t;
-    }
-    if (b > c)
-        b = c;
-    D.piv[k] = a > b ? a : b;
+    uint64_t p;
+    if (D.kind[slot] == 0)
+        p = D.jpivot[slot];
+    else if (D.pv[cur][k])
+        p = D.pv[cur][k];
+    else
+        p = sample_median64(reinterpret_cast<const T *>(base) + D.start[cur][k], D.len[cur][k], lane);
+    if (lane == 0)
+        D.piv[k] = p;
 }
 
 __device__ __forceinline__ uint32_t srv_emit(const SrvDev &D, uint32_t nxt, uint32_t slot, uint64_t s, uint64_t l,
@@ -194,7 +188,7 @@ __global__ void __launch_bounds__(256) k_schild(SrvDev D, uint32_t cur, const ui
 }
 
 template <typename T, int CAP, int KEYBITS>
-__global__ void __launch_bounds__(1024) k_sleaf(char *base, SrvDev D)
+__global__ void __launch_bounds__(kLeafNT) k_sleaf(char *base, SrvDev D)
 {
     const uint32_t n = D.count[2] < D.cap_leaves ? D.count[2] : D.cap_leaves;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -222,7 +216,7 @@ struct Server {
     SrvSub *dsub = nullptr;
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     hipEvent_t tick_ev[4] = {};
-    uint32_t stage_cap = 0, cur = 0, ticks_issued = 0, ticks_done = 0, leaf_grid = 0, seg_grid = 0;
+    uint32_t stage_cap = 0, cur = 0, ticks_issued = 0, ticks_done = 0, leaf_grid = 0, seg_grid = 0, seg_grid_w = 0;
     std::vector<SrvSub> pending;
 };
 
@@ -378,6 +372,7 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
         return fail_device(e, "hipMemsetAsync");
     }
     s->seg_grid = (uint32_t)((cap_segs + 255) / 256);
+    s->seg_grid_w = (uint32_t)((cap_segs + 3) / 4);
     *out = new ss_server{s};
     return SS_OK;
 }
@@ -444,9 +439,9 @@ extern "C" int ss_server_tick(ss_server *h, uint64_t max_len)
     }
     s->pending.clear();
     switch (s->dtype) {
-    case SS_U32: hipLaunchKernelGGL(k_sprep<uint32_t>, dim3(s->seg_grid), dim3(256), 0, st, s->base, s->D, cur); break;
-    case SS_U64: hipLaunchKernelGGL(k_sprep<uint64_t>, dim3(s->seg_grid), dim3(256), 0, st, s->base, s->D, cur); break;
-    default: hipLaunchKernelGGL(k_sprep<KV>, dim3(s->seg_grid), dim3(256), 0, st, s->base, s->D, cur); break;
+    case SS_U32: hipLaunchKernelGGL(k_sprep<uint32_t>, dim3(s->seg_grid_w), dim3(256), 0, st, s->base, s->D, cur); break;
+    case SS_U64: hipLaunchKernelGGL(k_sprep<uint64_t>, dim3(s->seg_grid_w), dim3(256), 0, st, s->base, s->D, cur); break;
+    default: hipLaunchKernelGGL(k_sprep<KV>, dim3(s->seg_grid_w), dim3(256), 0, st, s->base, s->D, cur); break;
     }
     BatchState B = s->B;
     B.start = s->D.start[cur];
@@ -466,19 +461,19 @@ extern "C" int ss_server_tick(ss_server *h, uint64_t max_len)
                                               : reinterpret_cast<const void *>(&k_sleaf<KV, 8192, 64>);
         int r2 = device_info(s->dev, &cus, &lds);
         if (!r2)
-            r2 = occupancy(s->dev, fn, 1024, &occ);
+            r2 = occupancy(s->dev, fn, kLeafNT, &occ);
         if (r2)
             return r2;
         s->leaf_grid = (uint32_t)(occ * cus);
     }
     switch (s->dtype) {
     case SS_U32:
-        hipLaunchKernelGGL((k_sleaf<uint32_t, 16384, 32>), dim3(s->leaf_grid), dim3(1024), 0, st, s->base, s->D);
+        hipLaunchKernelGGL((k_sleaf<uint32_t, 16384, 32>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D);
         break;
     case SS_U64:
-        hipLaunchKernelGGL((k_sleaf<uint64_t, 16384, 64>), dim3(s->leaf_grid), dim3(1024), 0, st, s->base, s->D);
+        hipLaunchKernelGGL((k_sleaf<uint64_t, 16384, 64>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D);
         break;
-    default: hipLaunchKernelGGL((k_sleaf<KV, 8192, 64>), dim3(s->leaf_grid), dim3(1024), 0, st, s->base, s->D); break;
+    default: hipLaunchKernelGGL((k_sleaf<KV, 8192, 64>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D); break;
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return fail_device(e, "tick launch");

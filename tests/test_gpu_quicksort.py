@@ -134,3 +134,47 @@ def test_quicksort_lds_engine(ss, kind):
         assert np.array_equal(o, r)
     else:
         assert np.array_equal(out, ref)
+
+
+def _leaf_inputs(kind, cap, rng):
+    """Segments that take each path of the workgroup sort: keys spread evenly
+    over a wide span (bucketed, a few keys per bucket), a narrow span of
+    repeated values (one key value per bucket, no insertion sort), and a
+    dense cluster with a far outlier (a bucket above the insertion limit, so
+    the radix sort runs), plus a span just above and just below 4096."""
+    dt = np.uint32 if kind == "u32" else np.uint64
+    top = np.iinfo(dt).max
+    segs = []
+    segs.append(rng.integers(0, top, size=cap, dtype=dt, endpoint=True))            # wide, even
+    segs.append(rng.integers(0, 100, size=cap - 3, dtype=dt))                        # narrow, repeated
+    c = rng.integers(1000, 1064, size=cap // 2 - 1, dtype=dt)                        # dense cluster
+    segs.append(np.concatenate([c, np.array([top, 0], dtype=dt), c[::-1]]))          # ... with outliers
+    segs.append(rng.integers(7, 7 + 4096, size=cap // 3, dtype=dt))                  # span below 2^12
+    segs.append(rng.integers(7, 7 + 4097 * 3, size=cap // 3 + 1, dtype=dt))          # span above 2^12
+    segs.append(rng.integers(5, 9, size=17, dtype=dt))                               # tiny
+    return segs
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64"])
+def test_sort_segments_leaf_paths(ss, kind):
+    rng = np.random.default_rng(12)
+    cap = ss.sort_segment_cap(ss.SS_U32 if kind == "u32" else ss.SS_U64)
+    segs = _leaf_inputs(kind, cap, rng)
+    gap = 13
+    starts, pos = [], 3
+    for s in segs:
+        starts.append(pos)
+        pos += len(s) + gap
+    data = np.zeros(pos, dtype=segs[0].dtype)
+    data[:] = rng.integers(0, 1 << 30, size=pos).astype(data.dtype)
+    for st, s in zip(starts, segs):
+        data[st:st + len(s)] = s
+    t = to_device(data)
+    ss.sort_segments(t, np.array(starts, dtype=np.uint64), np.array([len(s) for s in segs], dtype=np.uint64))
+    out = to_host(t, data)
+    expect = data.copy()
+    for st, s in zip(starts, segs):
+        ref = s.copy()
+        oracle.quicksort(ref)
+        expect[st:st + len(s)] = ref
+    assert np.array_equal(out, expect)   # sorted segments, untouched gaps
