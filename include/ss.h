@@ -66,7 +66,10 @@ enum ss_dtype { SS_U32 = 1, SS_U64 = 2, SS_KV16 = 3 };
  *               workgroup.
  * SS_LOWSPACE : the Low-Space implementation of the Blocked-Prefix-Sum
  *               partition (Section 3 with the explicit block-count array of
- *               Section 5.1); its auxiliary memory is about n/32 words.
+ *               Section 5.1); its auxiliary memory is two 32-bit words per
+ *               block of 64 elements (n/8 bytes): the block counts of the
+ *               array read forward and read reversed, both filled by the
+ *               preprocessing passes before the roles are known.
  * SS_HYBRID   : the Hybrid Smoothed Striding Algorithm (Section 4): one
  *               Partial Partition Step, then the Blocked-Prefix-Sum partition
  *               (SS_LOWSPACE) of the middle region [v_min, v_max).  The call

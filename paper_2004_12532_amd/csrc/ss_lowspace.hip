@@ -17,10 +17,15 @@
 //      (Lemma preprocessingphase): one launch per level while the level's
 //      prefix is larger than an LDS buffer, then one workgroup finishes every
 //      remaining level in LDS.
-//   4. Block counts of B = 64 elements (one wavefront ballot per block) and
-//      their exclusive prefix sums, stored explicitly (Section 5.1): per-block
-//      local prefixes within a workgroup's 1024 blocks plus one prefix per
-//      workgroup.
+//   4. Block counts of B = 64 elements and their exclusive prefix sums,
+//      stored explicitly (Section 5.1): per-block local prefixes within a
+//      workgroup's 1024 blocks plus one prefix per workgroup.  The counts
+//      cost no pass of their own: an element is final once the last
+//      preprocessing level that touches it is done, so each level's pass
+//      counts the part it leaves final, L[ceil(m/2), m) (the top level, run
+//      before the roles are known, counts both halves, one for each reading
+//      direction), and the LDS tail counts L[0, m).  Section 5.1 overlaps the
+//      counting with the preprocessing in the same way.
 //   5. In-place reordering (Section 3, "In-Place Reordering"): the prefix is
 //      cut repeatedly to its smallest block prefix holding more than 4/5 of
 //      its elements; the innermost prefix (at most one LDS buffer) is
@@ -64,6 +69,10 @@ struct Args {
     uint64_t *host;       // mapped host memory for the result (nullable)
     uint32_t whole;       // store whole vectors and blocks, changed or not (arrays far above the
                           // 256 MiB last-level cache, see kWholeLineBytes)
+    uint32_t fuse;        // the preprocessing passes also count each 64-element block's
+                          // predecessors (key < pivot) once its elements are final: into blk for
+                          // the logical array read forward, into cntr for it read reversed
+    uint32_t *cntr;
 };
 
 // Above this many bytes an array's passes store whole vectors and blocks, so
@@ -104,6 +113,36 @@ union Vec16 {
     T e[16 / sizeof(T)];
 };
 
+// Adds to C[b], for the blocks b of 64 logical elements that this wavefront's
+// elements fall in, how many of them are predecessors (key < pivot).  Lane
+// l holds V elements with block indices bi[e] and predecessor bits pm; the
+// wavefront's 64 V elements are consecutive, so they span at most V + 1
+// blocks: one ballot per (element, block) and one atomic per block.  Called
+// by every lane of the wavefront.
+template <int V>
+__device__ __forceinline__ void wave_block_add(uint32_t *C, const uint64_t (&bi)[V], uint32_t pm, bool ok)
+{
+    uint64_t lo = ~0ull;
+#pragma unroll
+    for (int e = 0; e < V; e++)
+        lo = ok && bi[e] < lo ? bi[e] : lo;
+    lo = wave_min(lo);
+    if (lo == ~0ull)
+        return;
+    const int lane = threadIdx.x & 63;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k <= V; k++) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int e = 0; e < V; e++)
+            c += (uint32_t)__popcll(__ballot(ok && ((pm >> e) & 1u) && bi[e] == lo + (uint64_t)k));
+        mine = lane == k ? c : mine;
+    }
+    if (lane <= V && mine)
+        atomicAdd(&C[lo + (uint64_t)lane], mine);
+}
+
 template <typename T, bool COUNT>
 __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_t m)
 {
@@ -111,11 +150,19 @@ __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_
     char *base = a.base;
     const uint64_t half = m / 2, nvec = half / V;
     const uint64_t stride = (uint64_t)gridDim.x * kNT;
+    const int lane = threadIdx.x & 63;
     uint64_t c = 0;
+    // Block counts of the elements this level leaves final: the back part
+    // L[ceil(m/2), m) into C; on the top level (roles not yet known, read
+    // forward) also the front part, into cntr at the blocks of the array read
+    // reversed, whose final part that is.
+    uint32_t *C = rev ? a.cntr : a.blk;
     // physical start of front / back vector t (see above)
     auto front_at = [&](uint64_t t) { return rev ? a.n - V * (t + 1) : V * t; };
     auto back_at = [&](uint64_t t) { return rev ? a.n - m + V * t : m - V * (t + 1); };
-    for (uint64_t t0 = (uint64_t)blockIdx.x * kNT + threadIdx.x; t0 < nvec; t0 += stride * kMirrorU) {
+    // w0: the wavefront's first vector, so every lane runs the same iterations
+    for (uint64_t w0 = (uint64_t)blockIdx.x * kNT + (threadIdx.x & ~63u); w0 < nvec; w0 += stride * kMirrorU) {
+        const uint64_t t0 = w0 + lane;
         Vec16<T> f[kMirrorU], b[kMirrorU];
 #pragma unroll
         for (int u = 0; u < kMirrorU; u++) {
@@ -128,27 +175,47 @@ __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_
 #pragma unroll
         for (int u = 0; u < kMirrorU; u++) {
             const uint64_t t = t0 + u * stride;
-            if (t >= nvec)
-                break;
+            if (w0 + u * stride >= nvec)
+                break;  // uniform: no lane of the wavefront has a vector left
+            const bool ok = t < nvec;
             bool any = false;
+            uint32_t pmb = 0, pmf = 0;  // predecessor bits after the swaps, by logical offset e
+            if (ok) {
 #pragma unroll
-            for (int e = 0; e < V; e++) {
-                // logical front element V t + e and its partner m - 1 - V t - e
-                T &x = f[u].e[rev ? V - 1 - e : e];
-                T &y = b[u].e[rev ? e : V - 1 - e];
-                const bool px = is_pred(x, a.pivot), py = is_pred(y, a.pivot);
-                if (COUNT)
-                    c += (uint64_t)px + (uint64_t)py;
-                if ((px != rev) && !(py != rev)) {
-                    const T tmp = x;
-                    x = y;
-                    y = tmp;
-                    any = true;
+                for (int e = 0; e < V; e++) {
+                    // logical front element V t + e and its partner m - 1 - V t - e
+                    T &x = f[u].e[rev ? V - 1 - e : e];
+                    T &y = b[u].e[rev ? e : V - 1 - e];
+                    const bool px = is_pred(x, a.pivot), py = is_pred(y, a.pivot);
+                    if (COUNT)
+                        c += (uint64_t)px + (uint64_t)py;
+                    const bool sw = (px != rev) && !(py != rev);
+                    if (sw) {
+                        const T tmp = x;
+                        x = y;
+                        y = tmp;
+                        any = true;
+                    }
+                    pmb |= (uint32_t)(sw ? px : py) << e;
+                    pmf |= (uint32_t)(sw ? py : px) << e;
+                }
+                if (a.whole || any) {
+                    *reinterpret_cast<v4u *>(base + front_at(t) * sizeof(T)) = f[u].v;
+                    *reinterpret_cast<v4u *>(base + back_at(t) * sizeof(T)) = b[u].v;
                 }
             }
-            if (a.whole || any) {
-                *reinterpret_cast<v4u *>(base + front_at(t) * sizeof(T)) = f[u].v;
-                *reinterpret_cast<v4u *>(base + back_at(t) * sizeof(T)) = b[u].v;
+            if (a.fuse) {
+                uint64_t bi[V];
+#pragma unroll
+                for (int e = 0; e < V; e++)
+                    bi[e] = (m - 1 - V * t - e) / kBlock;  // logical block of the partner
+                wave_block_add<V>(C, bi, pmb, ok);
+                if (COUNT) {
+#pragma unroll
+                    for (int e = 0; e < V; e++)
+                        bi[e] = (a.n - 1 - V * t - e) / kBlock;  // front element V t + e, array read reversed
+                    wave_block_add<V>(a.cntr, bi, pmf, ok);
+                }
             }
         }
     }
@@ -160,9 +227,16 @@ __device__ __forceinline__ uint64_t mirror_pass(const Args &a, bool rev, uint64_
         const bool pu_ = is_pred(u, a.pivot), pv_ = is_pred(v, a.pivot);
         if (COUNT)
             c += (uint64_t)pu_ + (uint64_t)pv_;
-        if ((pu_ != rev) && !(pv_ != rev)) {
+        const bool sw = (pu_ != rev) && !(pv_ != rev);
+        if (sw) {
             *pu = v;
             *pv = u;
+        }
+        if (a.fuse) {
+            if (sw ? pu_ : pv_)
+                atomicAdd(&C[(m - 1 - x) / kBlock], 1u);
+            if (COUNT && (sw ? pv_ : pu_))
+                atomicAdd(&a.cntr[(a.n - 1 - x) / kBlock], 1u);
         }
     }
     return c;
@@ -246,6 +320,17 @@ __global__ void __launch_bounds__(1024) k_pre_small(Args a)
     }
     for (uint32_t x = threadIdx.x; x < m0; x += 1024)
         *phys<T>(a, rev, x) = buf[x];
+    if (a.fuse) {
+        // every element of L[0, m0) is final: its blocks' predecessor counts
+        uint32_t *C = rev ? a.cntr : a.blk;
+        const int lane = threadIdx.x & 63;
+        for (uint32_t b = threadIdx.x >> 6; b * kBlock < m0; b += 1024 / 64) {
+            const uint32_t x = b * kBlock + lane;
+            const uint32_t cb = (uint32_t)__popcll(__ballot(x < m0 && is_pred(buf[x], a.pivot)));
+            if (lane == 0 && cb)
+                atomicAdd(&C[b], cb);
+        }
+    }
 }
 
 // Step 4a: per-block predecessor counts of L and their exclusive prefix
@@ -288,6 +373,64 @@ __global__ void __launch_bounds__(kNT) k_block_counts(Args a)
     if (lane == 63)
         wsum[wid] = inc;
     __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < wid; w++)
+        off += wsum[w];
+    uint32_t run = off + inc - s;
+    for (int k = 0; k < PER; k++) {
+        const uint64_t b = blk0 + threadIdx.x * PER + k;
+        if (b < nblk)
+            a.blk[b] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kNT - 1)
+        a.wgsum[blockIdx.x] = run;
+}
+
+// Step 4a with the counts fused into the preprocessing passes: both count
+// arrays start at zero.
+__global__ void __launch_bounds__(kNT) k_zero_counts(Args a)
+{
+    const uint64_t nblk = (a.n + kBlock - 1) / kBlock;
+    for (uint64_t b = (uint64_t)blockIdx.x * kNT + threadIdx.x; b < nblk; b += (uint64_t)gridDim.x * kNT) {
+        a.blk[b] = 0;
+        a.cntr[b] = 0;
+    }
+}
+
+// Step 4a, fused form: the passes left each block's count of keys below the
+// pivot in blk (L read forward) or cntr (L read reversed).  Turn it into the
+// block's count of predecessors of L (the complement within the block when
+// the roles are swapped) and its exclusive prefix within this workgroup's
+// kBlocksPerWg blocks, written over blk; the workgroup total into wgsum.
+__global__ void __launch_bounds__(kNT) k_block_prefix(Args a)
+{
+    __shared__ uint32_t wsum[kNT / 64];
+    const bool rev = a.ctl[1] != 0;
+    const uint32_t *C = rev ? a.cntr : a.blk;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kBlocksPerWg;
+    const uint64_t nblk = (a.n + kBlock - 1) / kBlock;
+    constexpr int PER = kBlocksPerWg / kNT;
+    uint32_t v[PER], s = 0;
+    for (int k = 0; k < PER; k++) {
+        const uint64_t b = blk0 + threadIdx.x * PER + k;
+        v[k] = 0;
+        if (b < nblk) {
+            const uint64_t bs = a.n - b * kBlock < (uint64_t)kBlock ? a.n - b * kBlock : (uint64_t)kBlock;
+            v[k] = rev ? (uint32_t)bs - C[b] : C[b];
+        }
+        s += v[k];
+    }
+    uint32_t inc = s;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d)
+            inc += y;
+    }
+    if (lane == 63)
+        wsum[wid] = inc;
+    __syncthreads();  // every count of this workgroup is read before blk is written
     uint32_t off = 0;
     for (int w = 0; w < wid; w++)
         off += wsum[w];
@@ -980,6 +1123,7 @@ struct LsWork {
     uint64_t *ctl = nullptr;
     uint64_t *wg_part = nullptr;
     uint32_t *blk = nullptr;
+    uint32_t *cntr = nullptr;   // block counts of the array read reversed (fused counting)
     uint64_t *wgsum = nullptr;
     size_t cap_n = 0;
     size_t bytes = 0;
@@ -1002,7 +1146,7 @@ size_t lowspace_aux_bytes(size_t n)
 {
     const size_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
     const size_t nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
-    return nblk * sizeof(uint32_t) + nwg * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + 8 * sizeof(uint64_t);
+    return 2 * nblk * sizeof(uint32_t) + nwg * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + 8 * sizeof(uint64_t);
 }
 
 // Steps 4'-5' of the implicit variant (after steps 1-3 on n > one LDS buffer).
@@ -1080,12 +1224,17 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     a.ctl = w.ctl;
     a.wg_part = w.wg_part;
     a.blk = w.blk;
+    a.cntr = w.cntr;
     a.wgsum = w.wgsum;
     const uint64_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
     a.nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
     a.d_split = d_split;
     a.host = ws->host_dev;
     a.whole = (uint64_t)n * sizeof(T) > ls::kWholeLineBytes ? 1u : 0u;
+    // The explicit path counts its blocks inside the preprocessing passes
+    // (Section 5.1 overlaps the counting with preprocessing).
+    const uint64_t small = ls::kSmallBytes / sizeof(T);
+    a.fuse = !pre_only && !(implicit && n > small) ? 1u : 0u;
     const uint64_t stream_grid = (uint64_t)cus * 8;
     auto grid_for = [&](uint64_t items) -> uint32_t {
         uint64_t g = (items + ls::kNT - 1) / ls::kNT;
@@ -1101,11 +1250,14 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
     // 1-2. count with the top preprocessing level, decide the roles
     const uint32_t g1 = mirror_grid(n) < kPartMax ? mirror_grid(n) : kPartMax;
     a.part_count = g1;
+    if (a.fuse) {
+        hipLaunchKernelGGL(ls::k_zero_counts, dim3(grid_for(nblk)), dim3(ls::kNT), 0, st, a);
+        (*launches)++;
+    }
     hipLaunchKernelGGL(ls::k_count_top<T>, dim3(g1), dim3(ls::kNT), 0, st, a);
     hipLaunchKernelGGL(ls::k_decide, dim3(1), dim3(ls::kNT), 0, st, a);
     *launches += 2;
     // 3. the other preprocessing levels
-    const uint64_t small = ls::kSmallBytes / sizeof(T);
     uint64_t m = (n + 1) / 2;
     while (m >= 2 && m > small) {
         a.m = m;
@@ -1113,7 +1265,7 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
         (*launches)++;
         m = (m + 1) / 2;
     }
-    if (m >= 2) {
+    if (m >= 2 || (a.fuse && m == 1)) {  // (m = 1: no level left, but L[0] still needs its count)
         a.m = m;
         hipLaunchKernelGGL(ls::k_pre_small<T>, dim3(1), dim3(1024), 0, st, a);
         (*launches)++;
@@ -1130,8 +1282,8 @@ static int lowspace_run(char *base, size_t n, uint64_t pivot, hipStream_t st, ui
             return fail_device(e, "implicit Blocked-Prefix-Sum kernel launch");
         return SS_OK;
     }
-    // 4. block counts and prefix sums
-    hipLaunchKernelGGL(ls::k_block_counts<T>, dim3((uint32_t)a.nwg), dim3(ls::kNT), 0, st, a);
+    // 4. block counts (left by the passes) and prefix sums
+    hipLaunchKernelGGL(ls::k_block_prefix, dim3((uint32_t)a.nwg), dim3(ls::kNT), 0, st, a);
     hipLaunchKernelGGL(ls::k_scan_wg, dim3(1), dim3(1024), 0, st, a);
     *launches += 2;
     // 5. reorder: prefixes N_0 = n > N_1 > ... > N_K <= one LDS buffer
@@ -1174,7 +1326,7 @@ static int ls_work(int dev, hipStream_t st, size_t n, LsWork **out)
         const size_t nblk = (n + ls::kBlock - 1) / ls::kBlock;
         const size_t nwg = (nblk + ls::kBlocksPerWg - 1) / ls::kBlocksPerWg;
         const size_t bytes = 8 * sizeof(uint64_t) + kPartMax * sizeof(uint64_t) + nwg * sizeof(uint64_t) +
-                             nblk * sizeof(uint32_t) + 256;
+                             2 * nblk * sizeof(uint32_t) + 256;
         char *p = nullptr;
         if ((e = hipMalloc((void **)&p, bytes)) != hipSuccess) {
             (void)hipGetLastError();
@@ -1184,6 +1336,7 @@ static int ls_work(int dev, hipStream_t st, size_t n, LsWork **out)
         w->wg_part = w->ctl + 8;
         w->wgsum = w->wg_part + kPartMax;
         w->blk = reinterpret_cast<uint32_t *>(w->wgsum + nwg);
+        w->cntr = w->blk + nblk;
         w->cap_n = n;
         w->bytes = bytes;
     }
