@@ -265,10 +265,10 @@ def run_partition(args, workload, algo="smoothed"):
                         "hybrid": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step before the "
                                   "Low-Space pass over the middle, exchange form)"}.get(algo)
                        if stats["exchange_mask"] & 1 else None) or
-                      {"smoothed": "k_level_rs<uint64_t,512,16,first> (first Partial Partition Step)",
-                       "strided": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step, offsets 0)",
+                      {"smoothed": "k_level_rs<uint64_t,512,16,first,staged> (first Partial Partition Step)",
+                       "strided": "k_level_rs<uint64_t,512,16,first,staged> (Partial Partition Step, offsets 0)",
                        "lowspace": "whole Low-Space call (all its kernels)",
-                       "hybrid": "k_level_rs<uint64_t,512,16,first> (Partial Partition Step before the "
+                       "hybrid": "k_level_rs<uint64_t,512,16,first,staged> (Partial Partition Step before the "
                                  "Low-Space pass over the middle)",
                        "mediumspace": "whole Medium-Space call (all its kernels and the copy back)",
                        "highspace": "whole High-Space call (all its kernels and the copy back)",
