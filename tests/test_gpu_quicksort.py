@@ -47,6 +47,11 @@ def test_quicksort_duplicates_and_orders(ss, kind):
         "ascending": np.sort(keys),
         "descending": np.sort(keys)[::-1].copy(),
         "few_distinct_1024": (workloads.keys_few_distinct_u32(n, 3, 1024).astype(keys.dtype)),
+        # periodic inputs whose period divides the pivot's sample spacing: every sampled key
+        # of a segment can be equal, so the pivot is extreme and only the key <= p pass progresses
+        "period_64": (np.arange(n) % 64).astype(keys.dtype),
+        "period_4096_sawtooth": (np.arange(n) % 4096).astype(keys.dtype) * 1000003,
+        "organ_pipe": np.minimum(np.arange(n), n - 1 - np.arange(n)).astype(keys.dtype),
     }
     for name, k in variants.items():
         a0 = base.copy()
