@@ -23,39 +23,56 @@ __device__ __forceinline__ uint64_t qkey(const T &x)
     return key_of(x);
 }
 
-// Threads of the workgroup that sorts one leaf.
-constexpr int kLeafNT = 1024;
+// Threads of the workgroups that sort leaves: the bucket sort of 4-byte keys
+// runs 512 threads in 80 KiB of LDS, so two workgroups share a compute unit
+// and one's loads and barriers overlap the other's work; 8-byte keys (144 KiB
+// of LDS) and the radix sort run 1024.
+template <typename T>
+constexpr int leaf_bucket_nt()
+{
+    return sizeof(T) == 4 ? 512 : 1024;
+}
+constexpr int kLeafRadixNT = 1024;
+
+// Plain keys (4 or 8 bytes), where equal keys are identical and stability
+// cannot be observed, are bucketed; records (KV16) take the radix sort.
+template <typename T>
+constexpr bool leaf_buckets()
+{
+    return sizeof(T) <= 8;
+}
 
 // Largest bucket the bucket sort below sorts by insertion; a leaf with a
-// larger one (and keys not all equal within buckets) takes the radix sort.
+// larger one (and keys not all equal within buckets) is left to the radix sort.
 constexpr uint32_t kLeafBucketMax = 32;
 
-// One workgroup (NT threads) sorts A[0, n), n <= CAP, by key.
+// One workgroup (NT threads) sorts A[0, n), n <= CAP, by key.  Returns true
+// when A is sorted; false only from the bucket sort, for a leaf it leaves
+// untouched because a bucket is crowded (the caller queues it for the radix
+// sort, which is a separate kernel so that the bucket kernel keeps few
+// registers).
 //
-// Plain keys (4 or 8 bytes, where equal keys are identical and stability
-// cannot be observed) are bucketed: bucket = (key - min) >> shift with 4096
-// buckets over the leaf's span, counted and scattered with LDS atomics, and
-// every bucket is then finished by an insertion sort (none is needed when
-// shift is 0: a bucket then holds one key value).  A leaf's keys come from
-// a narrow, evenly filled key range (the parts left by the partitions above
-// it), so buckets hold a few keys each; a leaf with a bucket above
-// kLeafBucketMax falls back to the radix sort.
+// Bucket sort (RADIX false): bucket = (key - min) >> shift with 4096 buckets
+// over the leaf's span, counted and scattered with LDS atomics, and every
+// bucket finished by an insertion sort (none is needed when shift is 0: a
+// bucket then holds one key value).  A leaf's keys come from a narrow,
+// evenly filled key range (the parts left by the partitions above it), so
+// buckets hold a few keys each.
 //
-// Records (KV16) and the fallback take the stable radix sort with 9-bit
-// digits.  Its counters share their LDS words with the bucket counters; the
-// per-wavefront minimum, maximum and scan totals sit in the element buffer,
-// which holds no element while they are live.  With 4-byte keys the
-// workgroup needs 80 KiB of LDS.
-template <typename T, int CAP, int KEYBITS, int NT = kLeafNT>
-__device__ void qleaf_sort(T *A, uint32_t n)
+// Radix sort (RADIX true): stable, 9-bit digits of key - min.
+//
+// The per-wavefront minimum, maximum and scan totals sit in the element
+// buffer, which holds no element while they are live.
+template <typename T, int CAP, int KEYBITS, int NT, bool RADIX>
+__device__ bool qleaf_sort(T *A, uint32_t n)
 {
     constexpr int NW = NT / 64;
     constexpr int E = CAP / NT;  // elements per thread
-    constexpr bool BUCKETS = sizeof(T) <= 8;
     constexpr int LOG2NB = 12, NB = 1 << LOG2NB, PB = NB / NT;
     constexpr int DBITS = 9, ND = 1 << DBITS;
-    constexpr int CW = NB > NW * ND / 2 ? NB : NW * ND / 2;  // 32-bit counter words
-    static_assert(ND <= NT && 64 * E < 65536 && NB % NT == 0, "digit counters: one digit per thread, 16-bit counts");
+    constexpr int CW = RADIX ? NW * ND / 2 : NB;  // 32-bit counter words
+    static_assert(!RADIX || (ND <= NT && 64 * E < 65536), "digit counters: one digit per thread, 16-bit counts");
+    static_assert(RADIX || (leaf_buckets<T>() && NB % NT == 0), "bucket sort: plain keys, whole buckets per thread");
     static_assert(CAP * sizeof(T) >= 2 * NW * 8 + 2 * NW * 4, "scratch inside the element buffer");
     __shared__ __align__(16) T buf[CAP];
     __shared__ uint32_t cw[CW];
@@ -88,7 +105,7 @@ __device__ void qleaf_sort(T *A, uint32_t n)
         red[wid] = kmin;
         red[NW + wid] = kmax;
     }
-    if constexpr (BUCKETS)
+    if constexpr (!RADIX)
         for (int j = tid; j < NB; j += NT)
             cw[j] = 0;
     __syncthreads();
@@ -108,9 +125,9 @@ __device__ void qleaf_sort(T *A, uint32_t n)
     auto rel = [&](const T &v) { return (K)qkey(v) - kmin_k; };
     if (nbits == 0) {
         __syncthreads();  // red is rewritten by the next leaf
-        return;           // every key is equal: the leaf is sorted
+        return true;      // every key is equal: the leaf is sorted
     }
-    if constexpr (BUCKETS) {
+    if constexpr (!RADIX) {
         const uint32_t shift = nbits > (uint32_t)LOG2NB ? nbits - (uint32_t)LOG2NB : 0u;
         for (int r = 0; r < E; r++)
             if (valid(r))
@@ -175,74 +192,76 @@ __device__ void qleaf_sort(T *A, uint32_t n)
                     A[idx] = buf[idx];
             }
             __syncthreads();  // LDS is reused by the next leaf
-            return;
+            return true;
         }
-        // a crowded bucket: the radix sort below reuses the counter words
-    }
-    for (uint32_t sh = 0; sh < nbits && sh < (uint32_t)KEYBITS; sh += DBITS) {
-        for (int d = lane; d < ND; d += 64)
-            cnt[wid][d] = 0;
-        // rank within the wavefront: lanes holding the same digit, in (round, lane) order
-        uint32_t pos[E];
-        for (int r = 0; r < E; r++) {
-            const uint32_t d = valid(r) ? (uint32_t)(rel(x[r]) >> sh) & (ND - 1) : 0u;
-            uint64_t m = __ballot(valid(r));
+        return false;  // a crowded bucket: A is untouched (the barrier above let every thread read wmax)
+    } else {
+        for (uint32_t sh = 0; sh < nbits && sh < (uint32_t)KEYBITS; sh += DBITS) {
+            for (int d = lane; d < ND; d += 64)
+                cnt[wid][d] = 0;
+            // rank within the wavefront: lanes holding the same digit, in (round, lane) order
+            uint32_t pos[E];
+            for (int r = 0; r < E; r++) {
+                const uint32_t d = valid(r) ? (uint32_t)(rel(x[r]) >> sh) & (ND - 1) : 0u;
+                uint64_t m = __ballot(valid(r));
 #pragma unroll
-            for (int bit = 0; bit < DBITS; bit++) {
-                const uint64_t bb = __ballot((d >> bit) & 1);
-                m &= ((d >> bit) & 1) ? bb : ~bb;
+                for (int bit = 0; bit < DBITS; bit++) {
+                    const uint64_t bb = __ballot((d >> bit) & 1);
+                    m &= ((d >> bit) & 1) ? bb : ~bb;
+                }
+                const uint32_t before = (uint32_t)__popcll(m & lt);
+                const uint32_t old = valid(r) ? cnt[wid][d] : 0u;
+                pos[r] = old + before;
+                if (valid(r) && before == 0)
+                    cnt[wid][d] = (uint16_t)(old + (uint32_t)__popcll(m));
             }
-            const uint32_t before = (uint32_t)__popcll(m & lt);
-            const uint32_t old = valid(r) ? cnt[wid][d] : 0u;
-            pos[r] = old + before;
-            if (valid(r) && before == 0)
-                cnt[wid][d] = (uint16_t)(old + (uint32_t)__popcll(m));
-        }
-        __syncthreads();
-        // destinations: digit-major, then wavefront, then rank within the wavefront.
-        // Thread t owns digit t: its total over the wavefronts, a scan over digits.
-        uint32_t tot = 0;
-        if (tid < ND)
-            for (int w = 0; w < NW; w++)
-                tot += cnt[w][tid];
-        uint32_t inc = tot;
+            __syncthreads();
+            // destinations: digit-major, then wavefront, then rank within the wavefront.
+            // Thread t owns digit t: its total over the wavefronts, a scan over digits.
+            uint32_t tot = 0;
+            if (tid < ND)
+                for (int w = 0; w < NW; w++)
+                    tot += cnt[w][tid];
+            uint32_t inc = tot;
 #pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
-            const uint32_t y = __shfl_up(inc, dd, 64);
-            if (lane >= dd)
-                inc += y;
-        }
-        if (lane == 63)
-            wsum[wid] = inc;
-        __syncthreads();
-        if (tid < ND) {
-            uint32_t run = inc - tot;
-            for (int w = 0; w < wid; w++)
-                run += wsum[w];
-            for (int w = 0; w < NW; w++) {
-                const uint32_t c = cnt[w][tid];
-                cnt[w][tid] = (uint16_t)run;
-                run += c;
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const uint32_t y = __shfl_up(inc, dd, 64);
+                if (lane >= dd)
+                    inc += y;
             }
+            if (lane == 63)
+                wsum[wid] = inc;
+            __syncthreads();
+            if (tid < ND) {
+                uint32_t run = inc - tot;
+                for (int w = 0; w < wid; w++)
+                    run += wsum[w];
+                for (int w = 0; w < NW; w++) {
+                    const uint32_t c = cnt[w][tid];
+                    cnt[w][tid] = (uint16_t)run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            for (int r = 0; r < E; r++)
+                if (valid(r))
+                    buf[cnt[wid][(uint32_t)(rel(x[r]) >> sh) & (ND - 1)] + pos[r]] = x[r];
+            __syncthreads();
+            for (int r = 0; r < E; r++) {
+                const uint32_t idx = base + r * 64;
+                if (valid(r))
+                    x[r] = buf[idx];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int r = 0; r < E; r++)
-            if (valid(r))
-                buf[cnt[wid][(uint32_t)(rel(x[r]) >> sh) & (ND - 1)] + pos[r]] = x[r];
-        __syncthreads();
         for (int r = 0; r < E; r++) {
             const uint32_t idx = base + r * 64;
             if (valid(r))
-                x[r] = buf[idx];
+                A[idx] = x[r];
         }
-        __syncthreads();
+        __syncthreads();  // LDS is reused by the next leaf
+        return true;
     }
-    for (int r = 0; r < E; r++) {
-        const uint32_t idx = base + r * 64;
-        if (valid(r))
-            A[idx] = x[r];
-    }
-    __syncthreads();  // LDS is reused by the next leaf
 }
 
 }  // namespace ss

@@ -71,6 +71,10 @@ __global__ void __launch_bounds__(256) k_qpivot(const char *base, const uint64_t
 // (at most CAP elements) is sorted by key by one workgroup.  The number of
 // leaves is *count when count is set, else nleaves.  When pub_dst is set,
 // workgroup 0 first writes the quicksort's per-level report to the host.
+// Plain keys take the bucket sort (k_qleaf); a leaf with a crowded bucket is
+// appended to fb (its index into the leaf list; *fb_count is zero before
+// k_qleaf) and sorted by the radix sort in k_qleaf_fb, launched right after.
+// Records take the radix sort in k_qleaf itself.
 struct QLeafArgs {
     char *base;
     const uint64_t *start, *len;
@@ -79,18 +83,44 @@ struct QLeafArgs {
     const uint32_t *pub_count;  // report: pub_dst[0] = *pub_count, pub_dst[1] = *pub_max
     const uint64_t *pub_max;
     uint64_t *pub_dst;
+    uint32_t *fb, *fb_count;    // leaves left to the radix sort (plain keys)
 };
 
 template <typename T, int CAP, int KEYBITS>
-__global__ void __launch_bounds__(kLeafNT) k_qleaf(QLeafArgs a)
+__global__ void __launch_bounds__(leaf_buckets<T>() ? leaf_bucket_nt<T>() : kLeafRadixNT) k_qleaf(QLeafArgs a)
 {
     if (a.pub_dst && blockIdx.x == 0 && threadIdx.x == 0) {
         a.pub_dst[0] = *a.pub_count;
         a.pub_dst[1] = *a.pub_max;
     }
     const uint32_t nleaves = a.count ? *a.count : a.nleaves;
-    for (uint32_t leaf = blockIdx.x; leaf < nleaves; leaf += gridDim.x)
-        qleaf_sort<T, CAP, KEYBITS>(reinterpret_cast<T *>(a.base) + a.start[leaf], (uint32_t)a.len[leaf]);
+    for (uint32_t leaf = blockIdx.x; leaf < nleaves; leaf += gridDim.x) {
+        T *A = reinterpret_cast<T *>(a.base) + a.start[leaf];
+        if constexpr (leaf_buckets<T>()) {
+            if (!qleaf_sort<T, CAP, KEYBITS, leaf_bucket_nt<T>(), false>(A, (uint32_t)a.len[leaf]) &&
+                threadIdx.x == 0)
+                a.fb[atomicAdd(a.fb_count, 1u)] = leaf;
+        } else {
+            qleaf_sort<T, CAP, KEYBITS, kLeafRadixNT, true>(A, (uint32_t)a.len[leaf]);
+        }
+    }
+}
+
+template <typename T, int CAP, int KEYBITS>
+__global__ void __launch_bounds__(kLeafRadixNT) k_qleaf_fb(QLeafArgs a)
+{
+    const uint32_t m = *a.fb_count;
+    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+        const uint32_t leaf = a.fb[k];
+        qleaf_sort<T, CAP, KEYBITS, kLeafRadixNT, true>(reinterpret_cast<T *>(a.base) + a.start[leaf],
+                                                        (uint32_t)a.len[leaf]);
+    }
+}
+
+__global__ void k_leaf_fb_reset(uint32_t *fb_count)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *fb_count = 0;
 }
 
 
@@ -163,35 +193,50 @@ hipError_t launch_qpivot(const char *base, const BatchState &B, uint32_t m, uint
     return hipGetLastError();
 }
 
-int qleaf_grid(int dtype)
+template <typename T, int CAP, int KEYBITS>
+static int leaf_grids(int *grid, int *grid_fb)
 {
-    static int grid[4] = {0, 0, 0, 0};
-    int &g = grid[dtype & 3];
-    if (!g) {
-        int dev = 0, cus = 0, lds = 0, occ = 0;
-        if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &cus, &lds) != SS_OK)
-            return 256;
-        const void *fn = dtype == SS_U32   ? reinterpret_cast<const void *>(&k_qleaf<uint32_t, 16384, 32>)
-                         : dtype == SS_U64 ? reinterpret_cast<const void *>(&k_qleaf<uint64_t, 16384, 64>)
-                                           : reinterpret_cast<const void *>(&k_qleaf<KV, 8192, 64>);
-        if (occupancy(dev, fn, kLeafNT, &occ) != SS_OK)
-            return 256;
-        g = occ * cus;
-    }
-    return g;
+    int dev = 0, cus = 0, lds = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &cus, &lds) != SS_OK)
+        return SS_EDEVICE;
+    const int nt = leaf_buckets<T>() ? leaf_bucket_nt<T>() : kLeafRadixNT;
+    if (occupancy(dev, reinterpret_cast<const void *>(&k_qleaf<T, CAP, KEYBITS>), nt, &occ) != SS_OK)
+        return SS_EDEVICE;
+    *grid = occ * cus;
+    if (occupancy(dev, reinterpret_cast<const void *>(&k_qleaf_fb<T, CAP, KEYBITS>), kLeafRadixNT, &occ) != SS_OK)
+        return SS_EDEVICE;
+    *grid_fb = occ * cus;
+    return SS_OK;
 }
 
-hipError_t launch_qleaf(int dtype, const QLeafArgs &a, hipStream_t st)
+// Sort the leaves of `a` (plain keys: the bucket kernel, then the radix
+// kernel over the leaves it left; a.fb_count must be zero).
+template <typename T, int CAP, int KEYBITS>
+static hipError_t launch_leaves(const QLeafArgs &a, hipStream_t st, uint32_t *launches)
 {
-    uint32_t grid = (uint32_t)qleaf_grid(dtype);
-    if (!a.count && a.nleaves < grid)
-        grid = a.nleaves ? a.nleaves : 1u;
-    switch (dtype) {
-    case SS_U32: hipLaunchKernelGGL((k_qleaf<uint32_t, 16384, 32>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
-    case SS_U64: hipLaunchKernelGGL((k_qleaf<uint64_t, 16384, 64>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_qleaf<KV, 8192, 64>), dim3(grid), dim3(kLeafNT), 0, st, a); break;
+    static int grid = 0, grid_fb = 0;
+    if (!grid && leaf_grids<T, CAP, KEYBITS>(&grid, &grid_fb) != SS_OK)
+        grid = grid_fb = 256;
+    uint32_t g = (uint32_t)grid;
+    if (!a.count && a.nleaves < g)
+        g = a.nleaves ? a.nleaves : 1u;
+    const int nt = leaf_buckets<T>() ? leaf_bucket_nt<T>() : kLeafRadixNT;
+    hipLaunchKernelGGL((k_qleaf<T, CAP, KEYBITS>), dim3(g), dim3(nt), 0, st, a);
+    (*launches)++;
+    if (leaf_buckets<T>()) {
+        hipLaunchKernelGGL((k_qleaf_fb<T, CAP, KEYBITS>), dim3((uint32_t)grid_fb), dim3(kLeafRadixNT), 0, st, a);
+        (*launches)++;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_qleaf(int dtype, const QLeafArgs &a, hipStream_t st, uint32_t *launches)
+{
+    switch (dtype) {
+    case SS_U32: return launch_leaves<uint32_t, 16384, 32>(a, st, launches);
+    case SS_U64: return launch_leaves<uint64_t, 16384, 64>(a, st, launches);
+    default: return launch_leaves<KV, 8192, 64>(a, st, launches);
+    }
 }
 
 // ------------------------------------------------------------ device-driven levels
@@ -209,6 +254,7 @@ struct QsCtl {
     uint64_t *leaf_start, *leaf_len;
     uint64_t *report;      // [0] segments of the next level, [1] the longest of them
     uint32_t *overflow;    // set if a list capacity would be exceeded (never, by the bounds below)
+    uint32_t *fb, *fb_count;  // leaves left to the radix sort (k_qleaf_fb)
     uint32_t cap_segs, cap_leaves;
     uint64_t leaf_cap;     // segments up to this length are leaves
 };
@@ -221,6 +267,7 @@ __global__ void k_qinit(SegList L, QsCtl C, uint64_t n)
         L.pv[0] = 0;
         *L.count = 1;
         *C.overflow = 0;
+        *C.fb_count = 0;
     }
 }
 
@@ -234,6 +281,7 @@ __global__ void __launch_bounds__(256) k_qprep(const char *base, SegList cur, Se
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *nxt.count = 0;
         *C.leaf_count = 0;
+        *C.fb_count = 0;
         C.report[1] = 0;
     }
     if (k >= *cur.count)
@@ -401,7 +449,8 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     // word layout of the workspace
     const size_t words = 2 * 3 * capS + capS /*piv*/ + 2 * capL /*leaves*/ + 3 * capS /*lo, hi, split*/ +
                          (capS + 1) /*first*/ + items /*vout*/ + (capS + 1) / 2 + 1 /*g*/ + (items + 1) / 2 /*imap*/ +
-                         capS / 8 + 1 /*cls*/ + 8 /*ctl*/ + 8 /*counts, report, overflow*/;
+                         capS / 8 + 1 /*cls*/ + 8 /*ctl*/ + 8 /*counts, report, overflow*/ +
+                         (capL + 1) / 2 + 1 /*fb*/;
     QsDev *W = nullptr;
     int rc = qs_dev_reserve(dev, st, words * sizeof(uint64_t), &W);
     if (rc)
@@ -412,7 +461,8 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
         p += nw;
         return q;
     };
-    uint32_t *counts = reinterpret_cast<uint32_t *>(take(2));  // [0] list A, [1] list B, [2] leaves, [3] overflow
+    // [0] list A, [1] list B, [2] leaves, [3] overflow, [4] leaves for the radix sort
+    uint32_t *counts = reinterpret_cast<uint32_t *>(take(3));
     SegList LA{take(capS), take(capS), take(capS), counts + 0};
     SegList LB{take(capS), take(capS), take(capS), counts + 1};
     QsCtl C;
@@ -421,6 +471,8 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     C.overflow = counts + 3;
     C.leaf_start = take(capL);
     C.leaf_len = take(capL);
+    C.fb = reinterpret_cast<uint32_t *>(take((capL + 1) / 2 + 1));
+    C.fb_count = counts + 4;
     C.report = take(2);
     C.cap_segs = (uint32_t)capS;
     C.cap_leaves = (uint32_t)capL;
@@ -444,10 +496,9 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
     (*launches)++;
     if (n <= cap) {
         // the whole array is one leaf
-        QLeafArgs a{base, LA.start, LA.len, nullptr, 1u, nullptr, nullptr, nullptr};
-        if ((e = launch_qleaf(dtype, a, st)) != hipSuccess)
+        QLeafArgs a{base, LA.start, LA.len, nullptr, 1u, nullptr, nullptr, nullptr, C.fb, C.fb_count};
+        if ((e = launch_qleaf(dtype, a, st, launches)) != hipSuccess)
             return fail_device(e, "leaf sort launch");
-        (*launches)++;
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return fail_device(e, "hipStreamSynchronize");
         return SS_OK;
@@ -477,10 +528,11 @@ int quicksort_run(char *base, size_t n, int dtype, const Resolved &R, hipStream_
         if (rc2)
             return rc2;
         hipLaunchKernelGGL(k_qchildren, dim3(grid_s), dim3(256), 0, st, cur, nxt, C, (const uint64_t *)B.split);
-        QLeafArgs a{base, C.leaf_start, C.leaf_len, C.leaf_count, 0u, nxt.count, C.report + 1, W->rep_dev + 2 * L};
-        if ((e2 = launch_qleaf(dtype, a, st)) != hipSuccess)
+        QLeafArgs a{base,         C.leaf_start,      C.leaf_len, C.leaf_count, 0u, nxt.count,
+                    C.report + 1, W->rep_dev + 2 * L, C.fb,       C.fb_count};
+        if ((e2 = launch_qleaf(dtype, a, st, launches)) != hipSuccess)
             return fail_device(e2, "leaf sort launch");
-        *launches += 3;
+        *launches += 2;
         if ((e2 = hipEventRecord(W->ev[L & 3], st)) != hipSuccess)
             return fail_device(e2, "hipEventRecord");
         return SS_OK;
@@ -588,7 +640,9 @@ static int upload_segments(int dev, hipStream_t st, const uint64_t *h_starts, co
                            QsWork **wout, uint64_t **d_starts, uint64_t **d_lens)
 {
     QsWork *w = nullptr;
-    int rc = qs_reserve(dev, st, 2 * num + 16, 16, 2 * num + 16, &w);
+    // device words: starts, lengths, then (ss_sort_segments) the leaf sort's
+    // radix list, num 32-bit entries and its count
+    int rc = qs_reserve(dev, st, 2 * num + (num + 1) / 2 + 16, 16, 2 * num + 16, &w);
     if (rc)
         return rc;
     hipError_t e;
@@ -686,8 +740,11 @@ extern "C" int ss_sort_segments(void *d_base, const uint64_t *h_starts, const ui
         return rc;
     if (num > 0xffffffffull)
         return fail_msg(SS_EINVAL, "too many segments");
-    QLeafArgs a{(char *)d_base, ds, dl, nullptr, (uint32_t)num, nullptr, nullptr, nullptr};
-    if ((e = launch_qleaf(dtype, a, st)) != hipSuccess)
+    uint32_t *fb = reinterpret_cast<uint32_t *>(w->dev + 2 * num), *fb_count = fb + num;
+    hipLaunchKernelGGL(k_leaf_fb_reset, dim3(1), dim3(64), 0, st, fb_count);
+    uint32_t launches = 0;
+    QLeafArgs a{(char *)d_base, ds, dl, nullptr, (uint32_t)num, nullptr, nullptr, nullptr, fb, fb_count};
+    if ((e = launch_qleaf(dtype, a, st, &launches)) != hipSuccess)
         return fail_device(e, "segment sort launch");
     return SS_OK;
 }

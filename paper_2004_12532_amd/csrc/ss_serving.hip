@@ -44,7 +44,8 @@ struct SrvSub {
 struct SrvDev {
     uint64_t *start[2], *len[2], *pv[2];
     uint32_t *job[2];
-    uint32_t *count;      // [0], [1] list counts, [2] leaves, [3] overflow flags
+    uint32_t *count;      // [0], [1] list counts, [2] leaves, [3] overflow flags, [4] leaves for the radix sort
+    uint32_t *fb;         // leaves the bucket sort left to the radix sort (indices into the leaf list)
     uint64_t *piv;
     uint64_t *leaf_start, *leaf_len;
     uint32_t *leaf_job;
@@ -108,6 +109,7 @@ __global__ void __launch_bounds__(256) k_sprep(const char *base, SrvDev D, uint3
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         D.count[cur ^ 1u] = 0;
         D.count[2] = 0;
+        D.count[4] = 0;
     }
     if (k >= D.count[cur])
         return;
@@ -187,12 +189,36 @@ __global__ void __launch_bounds__(256) k_schild(SrvDev D, uint32_t cur, const ui
     srv_finish(D, slot);
 }
 
+// Plain keys take the bucket sort; a leaf with a crowded bucket goes to the
+// radix sort in k_sleaf_fb, which finishes it.  Records take the radix sort.
 template <typename T, int CAP, int KEYBITS>
-__global__ void __launch_bounds__(kLeafNT) k_sleaf(char *base, SrvDev D)
+__global__ void __launch_bounds__(leaf_buckets<T>() ? leaf_bucket_nt<T>() : kLeafRadixNT) k_sleaf(char *base, SrvDev D)
 {
     const uint32_t n = D.count[2] < D.cap_leaves ? D.count[2] : D.cap_leaves;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        qleaf_sort<T, CAP, KEYBITS>(reinterpret_cast<T *>(base) + D.leaf_start[i], (uint32_t)D.leaf_len[i]);
+        T *A = reinterpret_cast<T *>(base) + D.leaf_start[i];
+        bool sorted;
+        if constexpr (leaf_buckets<T>())
+            sorted = qleaf_sort<T, CAP, KEYBITS, leaf_bucket_nt<T>(), false>(A, (uint32_t)D.leaf_len[i]);
+        else
+            sorted = qleaf_sort<T, CAP, KEYBITS, kLeafRadixNT, true>(A, (uint32_t)D.leaf_len[i]);
+        if (threadIdx.x == 0) {
+            if (sorted)
+                srv_finish(D, D.leaf_job[i]);
+            else
+                D.fb[atomicAdd(&D.count[4], 1u)] = i;
+        }
+    }
+}
+
+template <typename T, int CAP, int KEYBITS>
+__global__ void __launch_bounds__(kLeafRadixNT) k_sleaf_fb(char *base, SrvDev D)
+{
+    const uint32_t m = D.count[4];
+    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+        const uint32_t i = D.fb[k];
+        qleaf_sort<T, CAP, KEYBITS, kLeafRadixNT, true>(reinterpret_cast<T *>(base) + D.leaf_start[i],
+                                                        (uint32_t)D.leaf_len[i]);
         if (threadIdx.x == 0)
             srv_finish(D, D.leaf_job[i]);
     }
@@ -216,7 +242,8 @@ struct Server {
     SrvSub *dsub = nullptr;
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     hipEvent_t tick_ev[4] = {};
-    uint32_t stage_cap = 0, cur = 0, ticks_issued = 0, ticks_done = 0, leaf_grid = 0, seg_grid = 0, seg_grid_w = 0;
+    uint32_t stage_cap = 0, cur = 0, ticks_issued = 0, ticks_done = 0, leaf_grid = 0, leaf_grid_fb = 0, seg_grid = 0,
+             seg_grid_w = 0;
     std::vector<SrvSub> pending;
 };
 
@@ -284,8 +311,8 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
     const uint64_t cap_segs = max_segments, cap_leaves = 2ull * max_segments + 2;
     const uint64_t tile_elems = s->R.tile / s->R.w;
     const uint64_t items = server_items_cap(capacity, tile_elems, cap_segs);
-    const size_t words = 2 * (3 * cap_segs + cap_segs / 2 + 1) /*lists*/ + 2 /*counts*/ + cap_segs /*piv*/ +
-                         2 * cap_leaves + cap_leaves / 2 + 1 /*leaves*/ + max_jobs / 8 + 1 /*kind*/ +
+    const size_t words = 2 * (3 * cap_segs + cap_segs / 2 + 1) /*lists*/ + 3 /*counts*/ + cap_segs /*piv*/ +
+                         2 * cap_leaves + 2 * (cap_leaves / 2 + 1) /*leaves, radix list*/ + max_jobs / 8 + 1 /*kind*/ +
                          2 * (size_t)max_jobs /*jpivot, jstart*/ + max_jobs / 2 + 1 /*outstanding*/ +
                          3 * cap_segs /*lo, hi, split*/ + cap_segs + 1 /*first*/ + items /*vout*/ +
                          cap_segs / 2 + 1 /*g*/ + items / 2 + 1 /*imap*/ + cap_segs / 8 + 1 /*cls*/ + 8 /*ctl*/ +
@@ -320,11 +347,12 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
         D.pv[l] = take(cap_segs);
         D.job[l] = reinterpret_cast<uint32_t *>(take(cap_segs / 2 + 1));
     }
-    D.count = reinterpret_cast<uint32_t *>(take(2));
+    D.count = reinterpret_cast<uint32_t *>(take(3));
     D.piv = take(cap_segs);
     D.leaf_start = take(cap_leaves);
     D.leaf_len = take(cap_leaves);
     D.leaf_job = reinterpret_cast<uint32_t *>(take(cap_leaves / 2 + 1));
+    D.fb = reinterpret_cast<uint32_t *>(take(cap_leaves / 2 + 1));
     D.kind = reinterpret_cast<uint8_t *>(take(max_jobs / 8 + 1));
     D.jpivot = take(max_jobs);
     D.jstart = take(max_jobs);
@@ -366,7 +394,7 @@ extern "C" int ss_server_create(void *d_base, size_t capacity, int dtype, uint32
             return fail_device(e, "hipEventCreate");
         }
     // zero the counters (a fill kernel would do as well; this runs once, outside any graph)
-    if ((e = hipMemsetAsync(D.count, 0, 4 * sizeof(uint32_t), s->st)) != hipSuccess ||
+    if ((e = hipMemsetAsync(D.count, 0, 6 * sizeof(uint32_t), s->st)) != hipSuccess ||
         (e = hipMemsetAsync(D.outstanding, 0, (size_t)max_jobs * sizeof(uint32_t), s->st)) != hipSuccess) {
         server_free(s);
         return fail_device(e, "hipMemsetAsync");
@@ -406,6 +434,32 @@ extern "C" int ss_server_submit(ss_server *h, uint32_t slot, uint64_t start, uin
     }
     reinterpret_cast<volatile uint32_t *>(s->hmem)[slot] = 0;
     s->pending.push_back(SrvSub{start, len, pivot, slot, (uint32_t)kind});
+    return SS_OK;
+}
+
+// The tick's leaf sorts: the bucket kernel for plain keys, then the radix
+// kernel over the leaves it left (records: the radix kernel alone).
+template <typename T, int CAP, int KEYBITS>
+static int launch_sleaves(Server *s, hipStream_t st)
+{
+    constexpr bool BUCKETS = leaf_buckets<T>();
+    constexpr int NT = BUCKETS ? leaf_bucket_nt<T>() : kLeafRadixNT;
+    if (!s->leaf_grid) {
+        int cus = 0, lds = 0, occ = 0, occ_fb = 0;
+        int r2 = device_info(s->dev, &cus, &lds);
+        if (!r2)
+            r2 = occupancy(s->dev, reinterpret_cast<const void *>(&k_sleaf<T, CAP, KEYBITS>), NT, &occ);
+        if (!r2)
+            r2 = occupancy(s->dev, reinterpret_cast<const void *>(&k_sleaf_fb<T, CAP, KEYBITS>), kLeafRadixNT, &occ_fb);
+        if (r2)
+            return r2;
+        s->leaf_grid = (uint32_t)(occ * cus);
+        s->leaf_grid_fb = (uint32_t)(occ_fb * cus);
+    }
+    hipLaunchKernelGGL((k_sleaf<T, CAP, KEYBITS>), dim3(s->leaf_grid), dim3(NT), 0, st, s->base, s->D);
+    if (BUCKETS)
+        hipLaunchKernelGGL((k_sleaf_fb<T, CAP, KEYBITS>), dim3(s->leaf_grid_fb), dim3(kLeafRadixNT), 0, st, s->base,
+                           s->D);
     return SS_OK;
 }
 
@@ -454,27 +508,14 @@ extern "C" int ss_server_tick(ss_server *h, uint64_t max_len)
     if (rc)
         return rc;
     hipLaunchKernelGGL(k_schild, dim3(s->seg_grid), dim3(256), 0, st, s->D, cur, (const uint64_t *)B.split);
-    if (!s->leaf_grid) {
-        int cus = 0, lds = 0, occ = 0;
-        const void *fn = s->dtype == SS_U32   ? reinterpret_cast<const void *>(&k_sleaf<uint32_t, 16384, 32>)
-                         : s->dtype == SS_U64 ? reinterpret_cast<const void *>(&k_sleaf<uint64_t, 16384, 64>)
-                                              : reinterpret_cast<const void *>(&k_sleaf<KV, 8192, 64>);
-        int r2 = device_info(s->dev, &cus, &lds);
-        if (!r2)
-            r2 = occupancy(s->dev, fn, kLeafNT, &occ);
-        if (r2)
-            return r2;
-        s->leaf_grid = (uint32_t)(occ * cus);
-    }
+    int rc2;
     switch (s->dtype) {
-    case SS_U32:
-        hipLaunchKernelGGL((k_sleaf<uint32_t, 16384, 32>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D);
-        break;
-    case SS_U64:
-        hipLaunchKernelGGL((k_sleaf<uint64_t, 16384, 64>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D);
-        break;
-    default: hipLaunchKernelGGL((k_sleaf<KV, 8192, 64>), dim3(s->leaf_grid), dim3(kLeafNT), 0, st, s->base, s->D); break;
+    case SS_U32: rc2 = launch_sleaves<uint32_t, 16384, 32>(s, st); break;
+    case SS_U64: rc2 = launch_sleaves<uint64_t, 16384, 64>(s, st); break;
+    default: rc2 = launch_sleaves<KV, 8192, 64>(s, st); break;
     }
+    if (rc2)
+        return rc2;
     if ((e = hipGetLastError()) != hipSuccess)
         return fail_device(e, "tick launch");
     if ((e = hipEventRecord(s->tick_ev[s->ticks_issued & 3], st)) != hipSuccess)
