@@ -3,8 +3,8 @@
 // Responsibilities: argument validation (before any device work), the
 // per-(device, stream) workspace, the choice of kernel variant and grid, the
 // chain of Partial Partition Step launches of the recursion (Section 4,
-// Recursive Smoothed Striding), continuing the recursion from the host when
-// the device-side level budget runs out, and the per-call statistics.
+// Recursive Smoothed Striding), planned per call from n and closed by the
+// one-workgroup serial base case, and the per-call statistics.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
