@@ -185,3 +185,46 @@ def test_serving_large_jobs_default_budget(ss):
     s2 = Server(budget_bytes=4 << 30, keep_outputs=True)
     s2.run([solo], realtime=False)
     assert np.array_equal(s2.outputs[solo.job_id], mix_out)
+
+
+@pytest.mark.parametrize("kind", ["u32", "u64"])
+def test_engine_plain_key_sorts_and_partitions(ss, kind):
+    """A plain-key engine (its leaves take the bucket sort, and leaves with a crowded
+    bucket the separate radix kernel): sort jobs on uniform and on clustered keys with far
+    outliers, and a partition job, each against the oracle."""
+    import torch
+    dt = np.uint32 if kind == "u32" else np.uint64
+    top = int(np.iinfo(dt).max)
+    rng = np.random.default_rng(21)
+    uni = rng.integers(0, top, size=200000, dtype=dt, endpoint=True)
+    clustered = (1000 + rng.integers(0, 64, size=100000)).astype(dt)
+    clustered[rng.integers(0, clustered.size, size=50)] = top - rng.integers(0, 1000, size=50).astype(dt)
+    part = rng.integers(0, top, size=50000, dtype=dt, endpoint=True)
+    data = np.concatenate([uni, clustered, part])
+    starts = [0, uni.size, uni.size + clustered.size]
+    lens = [uni.size, clustered.size, part.size]
+    pivot = int(np.sort(part)[part.size // 3])
+    t = torch.from_numpy(data.view(np.int32 if kind == "u32" else np.int64).copy()).cuda()
+    eng = ss.ServerEngine(t, max_jobs=8, max_segments=64)
+    eng.submit(0, starts[0], lens[0], 1)
+    eng.submit(1, starts[1], lens[1], 1)
+    eng.submit(2, starts[2], lens[2], 0, pivot)
+    for _ in range(400):
+        eng.tick(max(lens))
+        assert eng.wait(0) == 0
+        if all(eng.done(k)[0] for k in range(3)):
+            break
+    assert all(eng.done(k)[0] for k in range(3))
+    out = t.cpu().numpy().view(dt)
+    for k in (0, 1):
+        ref = data[starts[k]:starts[k] + lens[k]].copy()
+        oracle.quicksort(ref)
+        assert np.array_equal(out[starts[k]:starts[k] + lens[k]], ref)
+    ref = part.copy()
+    split = oracle.partition(ref, pivot)
+    assert eng.done(2)[1] == split
+    gl, gr = oracle.sorted_sides(out[starts[2]:starts[2] + lens[2]], split)
+    rl, rr = oracle.sorted_sides(ref, split)
+    assert np.array_equal(gl, rl) and np.array_equal(gr, rr)
+    assert eng.status() == 0
+    eng.close()
