@@ -102,19 +102,21 @@ __global__ void __launch_bounds__(256) k_binit(BatchState B, BatchGeom Gm)
 // count ctl[0] and the count of open arrays ctl[1].  One workgroup; chunks of
 // kScanChunk entries are staged through LDS so that global reads and writes
 // are coalesced, and each thread scans kScanPer consecutive entries.
-constexpr int kScanNT = 1024, kScanPer = 8, kScanChunk = kScanNT * kScanPer;
+constexpr int kScanNT = 1024, kScanPer = 20, kScanChunk = kScanNT * kScanPer;
 
 struct ScanSmem {
     uint64_t wsum[kScanNT / 64], wopen[kScanNT / 64];
 };
 
 // Exclusive scan of g over all arrays by one workgroup of kScanNT threads.
-// Each thread takes kScanPer consecutive entries of a chunk with two 16-byte
-// loads and writes their kScanPer first-item offsets as four 16-byte stores,
-// so a wavefront reads 2 KiB and writes 4 KiB contiguously per chunk.
+// Each thread takes kScanPer consecutive entries of a chunk with 16-byte
+// loads and writes their kScanPer first-item offsets as 16-byte stores, so a
+// wavefront reads 5 KiB and writes 10 KiB contiguously per chunk; a chunk
+// covers 20480 arrays, so a batch of 20000 takes one round of the loop (each
+// round waits for its loads once).
 __device__ void scan_groups(const BatchState &B, ScanSmem &S)
 {
-    static_assert(kScanPer == 8, "two 16-byte loads of g per thread");
+    static_assert(kScanPer % 4 == 0, "16-byte loads of g");
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     uint64_t carry = 0, ocarry = 0;
     const uint32_t num = bnum(B);
@@ -122,10 +124,14 @@ __device__ void scan_groups(const BatchState &B, ScanSmem &S)
         const uint32_t j0 = c0 + (uint32_t)tid * kScanPer;
         uint32_t v[kScanPer];
         if (j0 + kScanPer <= num) {
-            const v4u a = *reinterpret_cast<const v4u *>(B.g + j0);
-            const v4u b = *reinterpret_cast<const v4u *>(B.g + j0 + 4);
-            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+#pragma unroll
+            for (int r = 0; r < kScanPer; r += 4) {
+                const v4u a = *reinterpret_cast<const v4u *>(B.g + j0 + r);
+                v[r] = a.x;
+                v[r + 1] = a.y;
+                v[r + 2] = a.z;
+                v[r + 3] = a.w;
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < kScanPer; r++)
@@ -410,19 +416,33 @@ __global__ void __launch_bounds__(NT, 4) k_blevel_lds(BatchState B, BatchGeom Gm
 
 // Arrays still open after the last level: one workgroup each partitions the
 // remaining region serially (block two-pointer exchange).
-// 32 KiB blocks per serial step, as in the single-array cleanup.
+// 32 KiB blocks per serial step, as in the single-array cleanup.  Workgroup b
+// takes arrays b, b + grid, ...: it reads the splits of 1024 of them at once
+// (one per thread) to find the open ones, then partitions those in turn.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_bcleanup(BatchState B, BatchGeom Gm)
 {
     __shared__ CleanupSmem<T, 1024, 32768> S;
-    const uint32_t num = bnum(B);
-    for (uint32_t k = blockIdx.x; k < num; k += gridDim.x) {
-        if (B.split[k] != ~0ull)
-            continue;
-        const uint64_t sp = cleanup_region<T, 1024, 32768>(reinterpret_cast<T *>(Gm.base), B.pivot[k], B.lo[k],
-                                                            B.hi[k], S);
-        if (threadIdx.x == 0)
-            B.split[k] = sp;
+    __shared__ uint32_t open[1024];
+    __shared__ uint32_t n_open;
+    const uint32_t num = bnum(B), tid = threadIdx.x, step = gridDim.x;
+    for (uint64_t k0 = blockIdx.x; k0 < num; k0 += 1024ull * step) {
+        if (tid == 0)
+            n_open = 0;
+        __syncthreads();
+        const uint64_t k = k0 + (uint64_t)tid * step;
+        if (k < num && B.split[k] == ~0ull)
+            open[atomicAdd(&n_open, 1u)] = (uint32_t)k;
+        __syncthreads();
+        const uint32_t m = n_open;
+        for (uint32_t j = 0; j < m; j++) {
+            const uint32_t a = open[j];
+            const uint64_t sp =
+                cleanup_region<T, 1024, 32768>(reinterpret_cast<T *>(Gm.base), B.pivot[a], B.lo[a], B.hi[a], S);
+            if (tid == 0)
+                B.split[a] = sp;
+        }
+        __syncthreads();  // open and n_open are rewritten for the next arrays
     }
 }
 
@@ -546,6 +566,25 @@ uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems)
     return lv == 1 ? 1u : lv + 1;
 }
 
+// Levels of a batched call with the tail geometry, planned as for a single
+// array: the first level leaves about 4.4 / sqrt(S0) of an array of max_len
+// elements, each later one about 0.11 of the region before it, until the
+// expected region fits two passes of the closing serial cleanup (k_bcleanup),
+// which partitions whatever is still open.
+uint32_t batched_planned_levels(uint64_t max_len, uint64_t S0, int w)
+{
+    if (max_len <= S0)
+        return 1;
+    const double base = 2.0 * (double)cleanup_pass_elems(w);
+    double r = (double)max_len * 4.4 / std::sqrt((double)S0);
+    uint32_t lv = 1;
+    while (r > base && lv < 16) {
+        r *= 0.11;
+        lv++;
+    }
+    return lv;
+}
+
 // Run the batched recursion for `num` arrays whose start/len are already in
 // device memory (B.start, B.len): `levels` persistent level launches, then
 // the cleanup of any array still open, then (if d_splits) the splits
@@ -561,8 +600,23 @@ BatchClasses batched_default_classes(const Resolved &R)
     return C;
 }
 
+// The geometry of a batched call's levels from the second on: every class
+// (the table keeps its class count, so each array's class index stays valid)
+// takes 32 KiB groups of 128-byte lines, as the single-array path does for
+// its small late regions.  There the regions are small and a group is bound
+// by latency, so more, shorter groups keep more of them in flight.
+BatchClasses batched_tail_classes(const BatchClasses &BC, int w)
+{
+    BatchClasses T = BC;
+    for (uint32_t c = 0; c < T.n; c++) {
+        T.log2b[c] = (uint32_t)ilog2(128u / (uint32_t)w);
+        T.s_max[c] = kTailGroupBytes / 128u;
+    }
+    return T;
+}
+
 int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B, uint32_t levels,
-                 hipStream_t st, uint64_t *d_splits, uint32_t *launches)
+                 hipStream_t st, uint64_t *d_splits, uint32_t *launches, const BatchClasses *tailC)
 {
     hipError_t e;
     int dev = 0;
@@ -584,6 +638,17 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
     for (uint32_t c = 0; c < BC.n; c++)
         if (((uint64_t)BC.s_max[c] << BC.log2b[c]) * R.w > tile || !BC.s_max[c])
             return fail_msg(SS_EINVAL, "size class geometry exceeds the batched kernel's tile");
+    // Levels from the second on with the tail geometry (tailC): its own kernel
+    // variant of 32 KiB groups.
+    const BVariant *Vt = tailC ? pick_bvariant(dtype, SS_ENGINE_REGS, kTailGroupBytes) : nullptr;
+    uint32_t Pt = 0;
+    if (tailC) {
+        if (!Vt)
+            return fail_msg(SS_EUNSUPPORTED, "no batched tail kernel variant");
+        if ((rc = occupancy(dev, Vt->fn(), Vt->nt, &occ)))
+            return rc;
+        Pt = (uint32_t)(occ * cus);
+    }
     BatchGeom Gm;
     Gm.base = base;
     Gm.seed = R.seed;
@@ -596,8 +661,16 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
         levels = 1;
     // (the LDS-tile kernel keeps its table small: its occupancy is bound by LDS)
     Gm.search = B.num < (engine == SS_ENGINE_LDS ? 1024u : tile == 131072u ? kSearchMaxBig : kSearchMaxSmall);
+    const bool search0 = Gm.search;
     for (uint32_t level = 0; level < levels; level++) {
         Gm.level = level;
+        const bool tail = tailC && level >= 1;
+        if (tail) {
+            Gm.C = *tailC;
+            Gm.search = B.num < kSearchMaxSmall;
+        } else {
+            Gm.search = search0;
+        }
         if (level == 0)
             hipLaunchKernelGGL(k_binit, dim3(nb256), dim3(256), 0, st, B, Gm);
         else
@@ -608,7 +681,7 @@ int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &B
             hipLaunchKernelGGL(k_bfill, dim3(nb4), dim3(256), 0, st, B);
             (*launches)++;
         }
-        if ((e = V->launch(P, B, Gm, st)) != hipSuccess)
+        if ((e = tail ? Vt->launch(Pt, B, Gm, st) : V->launch(P, B, Gm, st)) != hipSuccess)
             return fail_device(e, "batched level launch");
         (*launches)++;
     }
@@ -757,7 +830,8 @@ constexpr size_t kMaxGraphs = 64;
 }  // namespace
 
 int batched_graph(int dev, char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B,
-                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches)
+                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches,
+                  const BatchClasses *tailC)
 {
     std::lock_guard<std::mutex> lk(g_gr_mu);
     // The engine picks the kernel bodies and the class table is baked into the
@@ -766,6 +840,7 @@ int batched_graph(int dev, char *base, int dtype, const Resolved &R, const Batch
     const unsigned char *cb = reinterpret_cast<const unsigned char *>(&BC);
     for (size_t j = 0; j < sizeof(BC); j++)
         h = (h ^ cb[j]) * 1099511628211ull;
+    h = (h ^ (tailC ? 1u : 0u)) * 1099511628211ull;  // the tail geometry changes the kernels of later levels
     GraphKey key{dev, (void *)st, base, B.pivot, d_splits, B.ctl, dtype, B.num, levels, R.tile, R.engine,
                  R.flags & ~(uint32_t)SS_FLAG_TIME, items_cap, R.seed, h};
     hipError_t e;
@@ -777,7 +852,7 @@ int batched_graph(int dev, char *base, int dtype, const Resolved &R, const Batch
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return fail_device(e, "hipStreamBeginCapture");
         uint32_t n_launch = 0;
-        const int rc = batched_core(base, dtype, R, BC, B, levels, cs, d_splits, &n_launch);
+        const int rc = batched_core(base, dtype, R, BC, B, levels, cs, d_splits, &n_launch, tailC);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         if (rc) {
@@ -856,9 +931,17 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         BC = batched_default_classes(R);
         batched_installed_classes(dev, dtype, R, &BC);
     }
+    // Levels from the second on take the tail geometry (32 KiB groups of
+    // 128-byte lines) on the 128 KiB register body: a batch's arrays are
+    // mostly short, their middle regions after the first level hold a few
+    // hundred elements, and a level over them is bound by the latency of its
+    // groups.  The choice depends only on the parameters, never on the batch,
+    // so an array's bytes stay the same alone and in any batch.
+    const BatchClasses TC = batched_tail_classes(BC, R.w);
+    const bool use_tail = R.engine == SS_ENGINE_REGS && R.tile == 131072u;
     // Items (groups) per array at any level: at most len / (group elements) + 3.
     uint64_t max_len[kMaxClasses] = {0};
-    uint64_t items_cap = 64;
+    uint64_t items_cap = 64, items_tail = 64;
     for (size_t k = 0; k < num; k++) {
         if ((rc = check_lines(lens[k], R)))
             return rc;
@@ -866,11 +949,16 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
         while (c + 1 < BC.n && lens[k] > BC.max_len[c])
             c++;
         max_len[c] = lens[k] > max_len[c] ? lens[k] : max_len[c];
-        items_cap += lens[k] / ((uint64_t)BC.s_max[c] << BC.log2b[c]) + 3;
+        const uint64_t S0 = (uint64_t)BC.s_max[c] << BC.log2b[c];
+        items_cap += lens[k] / S0 + 3;
+        items_tail += lens[k] / ((uint64_t)TC.s_max[c] << TC.log2b[c]) + 3;
     }
+    if (use_tail && items_tail > items_cap)
+        items_cap = items_tail;
     uint32_t levels = 1;
     for (uint32_t c = 0; c < BC.n; c++) {
-        const uint32_t lv = batched_levels(max_len[c], (uint64_t)BC.s_max[c] << BC.log2b[c]);
+        const uint64_t S0 = (uint64_t)BC.s_max[c] << BC.log2b[c];
+        const uint32_t lv = use_tail ? batched_planned_levels(max_len[c], S0, R.w) : batched_levels(max_len[c], S0);
         levels = lv > levels ? lv : levels;
     }
     if (p && p->max_levels)
@@ -895,10 +983,11 @@ static int batched_segments(void *d_base, const uint64_t *starts, const uint64_t
             return fail_msg(SS_EDEVICE, "hipEventCreate");
         (void)hipEventRecord(t0, st);
     }
+    const BatchClasses *tc = use_tail ? &TC : nullptr;
     if (R.flags & SS_FLAG_GRAPH)
-        rc = batched_graph(dev, (char *)d_base, dtype, R, BC, B, items_cap, levels, st, d_splits, &ro.launches);
+        rc = batched_graph(dev, (char *)d_base, dtype, R, BC, B, items_cap, levels, st, d_splits, &ro.launches, tc);
     else
-        rc = batched_core((char *)d_base, dtype, R, BC, B, levels, st, d_splits, &ro.launches);
+        rc = batched_core((char *)d_base, dtype, R, BC, B, levels, st, d_splits, &ro.launches, tc);
     if (rc)
         return rc;
     if (timing) {

@@ -151,15 +151,21 @@ int batched_state(int dev, void *stream, uint32_t num, uint64_t items_cap, Batch
                   hipEvent_t *stage_copied);
 uint64_t batched_items_cap(const uint64_t *lens, uint32_t num, uint64_t tile_elems);
 uint32_t batched_levels(uint64_t max_len, uint64_t tile_elems);
+uint32_t batched_planned_levels(uint64_t max_len, uint64_t S0, int w);
 int batched_graph(int dev, char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B,
-                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches);
+                  uint64_t items_cap, uint32_t levels, hipStream_t st, uint64_t *d_splits, uint32_t *launches,
+                  const BatchClasses *tailC = nullptr);
 void batched_graphs_forget(const void *state);
 BatchClasses batched_default_classes(const Resolved &R);
 void batched_installed_classes(int dev, int dtype, const Resolved &R, BatchClasses *C);
 bool batched_has_tuning(int dev, int dtype);
 uint32_t batched_auto_engine(int dtype);
+// Group bytes of the tail geometry (levels from the second on, when a caller
+// asks for it: batched_tail_classes).
+constexpr uint32_t kTailGroupBytes = 32768;
+BatchClasses batched_tail_classes(const BatchClasses &BC, int w);
 int batched_core(char *base, int dtype, const Resolved &R, const BatchClasses &BC, BatchState &B, uint32_t levels,
-                 hipStream_t st, uint64_t *d_splits, uint32_t *launches);
+                 hipStream_t st, uint64_t *d_splits, uint32_t *launches, const BatchClasses *tailC = nullptr);
 
 uint64_t quicksort_leaf_cap(int dtype);
 
