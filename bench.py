@@ -216,6 +216,9 @@ def run_partition(args, workload, algo="smoothed"):
 
     traffic = counter_traffic(workload) if (algo == "smoothed" and exchange == "auto"
                                             and not args.b and not args.tile_bytes) else None
+    # the exchange kernel: 512 threads per 32 KiB group when the library chooses the form, the
+    # forced form's 256-thread shape otherwise
+    xshape = ("512,4", " chosen from the key sample") if exchange == "auto" else ("256,8", "")
     out = {
         "metric": "partition GB/s & % HBM peak, 2^30 u64; batched vs per-array launch; p99 latency",
         "value": round(value, 2),
@@ -258,12 +261,12 @@ def run_partition(args, workload, algo="smoothed"):
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "frac_of_probe": round(achieved / probe["rw_GBps"], 4) if probe else None,
             "traffic": traffic,
-            "kernel": ({"smoothed": "k_level_rs<uint64_t,256,8,first,exchange> (first Partial Partition Step, "
-                                    "write-minimal exchange form chosen from the key sample)",
-                        "strided": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step, offsets 0, "
-                                   "exchange form)",
-                        "hybrid": "k_level_rs<uint64_t,256,8,first,exchange> (Partial Partition Step before the "
-                                  "Low-Space pass over the middle, exchange form)"}.get(algo)
+            "kernel": ({"smoothed": "k_level_rs<uint64_t,%s,first,exchange> (first Partial Partition Step, "
+                                    "write-minimal exchange form%s)" % xshape,
+                        "strided": "k_level_rs<uint64_t,%s,first,exchange> (Partial Partition Step, offsets 0, "
+                                   "exchange form%s)" % xshape,
+                        "hybrid": "k_level_rs<uint64_t,%s,first,exchange> (Partial Partition Step before the "
+                                  "Low-Space pass over the middle, exchange form%s)" % xshape}.get(algo)
                        if stats["exchange_mask"] & 1 else None) or
                       {"smoothed": "k_level_rs<uint64_t,512,16,first,staged> (first Partial Partition Step)",
                        "strided": "k_level_rs<uint64_t,512,16,first,staged> (Partial Partition Step, offsets 0)",

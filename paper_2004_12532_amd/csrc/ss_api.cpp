@@ -214,6 +214,17 @@ int resolve_params(const ss_params *p, int dtype, Resolved *r, uint32_t auto_eng
      SS_RS_FORMS(&level_rs_fn_t, T, NT, NV),                                                              \
      {level_form_lds<T, NT, NV, kFormDirect>(), level_form_lds<T, NT, NV, kFormExchange>(),              \
       level_form_lds<T, NT, NV, kFormStaged>()}}
+// The automatic choice's exchange kernel: 32 KiB groups over 512 threads
+// (four vectors a thread), so each wavefront ranks and swaps half as many
+// elements per group as with 256 threads.
+#define SS_XCH_VARIANT(D, T, NT, NV)                                                      \
+    {D,                                                                                   \
+     kEngineAutoExchange,                                                                 \
+     NT * NV * 16,                                                                        \
+     NT,                                                                                  \
+     {nullptr, &launch_level_rs_t<T, NT, NV, kFormExchange>, nullptr},                    \
+     {nullptr, &level_rs_fn_t<T, NT, NV, kFormExchange>, nullptr},                        \
+     {0, level_form_lds<T, NT, NV, kFormExchange>(), 0}}
 #define SS_RS_ALL(NT, NV) \
     SS_RS_VARIANT(SS_U32, uint32_t, NT, NV), SS_RS_VARIANT(SS_U64, uint64_t, NT, NV), SS_RS_VARIANT(SS_KV16, KV, NT, NV)
 
@@ -225,6 +236,7 @@ const Variant *pick_variant(int dtype, uint32_t engine, uint32_t tile)
         SS_LDS_VARIANT(SS_U64, uint64_t, 256, 32768), SS_LDS_VARIANT(SS_KV16, KV, 256, 32768),
         SS_RS_ALL(256, 8),                            SS_RS_ALL(512, 8),
         SS_RS_ALL(512, 16),
+        SS_XCH_VARIANT(SS_U64, uint64_t, 512, 4),     SS_XCH_VARIANT(SS_KV16, KV, 512, 4),
     };
     for (const Variant &x : v)
         if (x.dtype == dtype && x.engine == engine && x.tile == tile)
@@ -350,7 +362,7 @@ int run_partition(char *base, size_t n, int dtype, uint64_t pivot, const Resolve
     const int fx = kFormExchange;
     uint32_t Px = 0;
     if (autox) {
-        Vx = pick_variant(dtype, SS_ENGINE_REGS, 32768u);
+        Vx = pick_variant(dtype, kEngineAutoExchange, 32768u);
         if (!Vx || !Vx->launch[fx])
             return fail_msg(SS_EUNSUPPORTED, "no exchange variant");
         if ((rc = grid_of(Vx->fn[fx](true), Vx->nt, Vx->lds[fx], &Px)))

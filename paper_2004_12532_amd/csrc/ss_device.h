@@ -65,6 +65,35 @@ struct Elem<KV> {
     __device__ static __forceinline__ void store1(const v4u &v, int, char *p) { *reinterpret_cast<v4u *>(p) = v; }
 };
 
+// Inclusive prefix sum over the wavefront's 64 lanes: Hillis-Steele steps
+// inside each row of 16 lanes (DPP row shifts by 1, 2, 4 and 8; a lane
+// whose source lies before its row's start adds 0), then the totals of the
+// rows below, read from lanes 15, 31 and 47.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x, int lane)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+    const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+    const int row = lane >> 4;
+    return x + (row >= 1 ? t0 : 0u) + (row >= 2 ? t1 : 0u) + (row >= 3 ? t2 : 0u);
+}
+
+// A workgroup barrier that orders LDS accesses only: every wavefront's LDS
+// reads and writes before it are complete, and the compiler moves no memory
+// access across it.  Global loads and stores stay in flight (a barrier with
+// the default fence waits for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xf | 0x3 << 14 | 0x7 << 4);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

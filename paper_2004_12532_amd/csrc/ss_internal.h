@@ -21,6 +21,9 @@ constexpr uint32_t kDefaultLineBytes = 512;
 constexpr uint32_t kExchangeFlags = SS_FLAG_EXCHANGE | SS_FLAG_EXCHANGE_SKEWED;
 constexpr uint32_t kSkewShift = 5;  // skewed: misplaced pairs at most 1/32 of a group's slots
 constexpr uint64_t kAutoExchangeMin = 1ull << 22;  // automatic exchange choice from this many elements on
+// Engine id of the kernel shapes that serve only the exchange form of the
+// automatic first-level choice (not a public SS_ENGINE_* value).
+constexpr uint32_t kEngineAutoExchange = 0x100;
 constexpr int kResultWrittenFirst = 5;  // result word: elements stored by a first level in the exchange form
 constexpr int kResultWritten = 6;   // result word: elements stored by later exchange-form levels
 constexpr int kResultGate = 7;      // result word: 1 when the exchange form was chosen

@@ -25,7 +25,8 @@
 // With the write-minimal exchange (SS_FLAG_EXCHANGE) step (4) instead swaps
 // the misplaced pairs of the group through a table of slot numbers in LDS
 // and writes only those elements: at a skewed pivot most lines are never
-// written.
+// written.  With groups of at most 32 KiB the exchange stages the group in
+// an LDS tile and issues the next group's loads before ranking it.
 //
 // A group whose lines are all real and that fills the whole tile (every
 // group of a level except at most the two touching the region's ends, and
@@ -41,13 +42,24 @@
 
 namespace ss {
 
+// The exchange form with groups of at most 32 KiB stages each group in an
+// LDS tile and loads the next group into registers while the current one is
+// ranked and swapped (its barriers wait for LDS only), so HBM reads stay in
+// flight through the exchange's passes.
+template <typename T, int NT, int NV, int FORM>
+constexpr bool xch_prefetch()
+{
+    return FORM == kFormExchange && NT * NV * 16 <= 32768;
+}
+
 // Store forms: kForm* in ss_common.h.
 template <typename T, int NT, int NV, bool FIRST, int FORM>
 __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
 {
     constexpr bool XCH = FORM == kFormExchange;
     constexpr bool STAGED = FORM == kFormStaged;
-    using Ctx = LevelCtx<T, NT, NV>;
+    constexpr bool PREFETCH = xch_prefetch<T, NT, NV, FORM>();
+    using Ctx = LevelCtx<T, NT, NV, PREFETCH>;
     constexpr int W = Ctx::W;
     constexpr int NW = Ctx::NW;
     constexpr int MAXS = Ctx::NVEC * 16 / 64;  // lines of at least 64 bytes
@@ -157,7 +169,7 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
         }
     };
     using Mask = typename Ctx::Mask;
-    auto load_any = [&](v4u (&buf)[NV], uint32_t i, Mask &m) -> bool {
+    auto load_any = [&](v4u (&buf)[NV], uint32_t i, Mask &m) __attribute__((always_inline)) -> bool {
         const bool f = x.fast(i);
         if (f)
             x.template load<true>(buf, i, m);
@@ -165,7 +177,8 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             x.template load<false>(buf, i, m);
         return f;
     };
-    // dynamic LDS: the exchange table (Ctx::XCH_BYTES) or the staging tile (NVEC vectors)
+    // dynamic LDS: the exchange table (Ctx::XCH_BYTES; with 32 KiB groups two
+    // of them, then the group's tile) or the staging tile (NVEC vectors)
     extern __shared__ v4u dyn_lds[];
     uint16_t *const xt = reinterpret_cast<uint16_t *>(dyn_lds);
     uint64_t written = 0;             // exchange form: elements this workgroup stored
@@ -177,14 +190,61 @@ __global__ void __launch_bounds__(NT) k_level_rs(const LevelArgs a)
             return f ? x.template partition<true>(buf, i, m) : x.template partition<false>(buf, i, m);
     };
 
+    const uint32_t step = gridDim.x;
+    uint32_t i = bid;
+    if constexpr (PREFETCH) {
+        // The group is staged into an LDS tile after the exchange tables (two
+        // of S / 2 slots), and the next group's loads are issued into the
+        // registers as soon as the tile is written, so that they are in flight
+        // while the group is ranked and swapped (its barriers wait for LDS
+        // only).  A group that is not wholly real (at most the two at the
+        // region's ends) or that may fall back to the stable form takes the
+        // register-resident exchange below, then issues the next loads.
+        v4u *const tile = dyn_lds + 2 * Ctx::XCH_BYTES / 16;
+        v4u buf[NV];
+        Mask m;
+        bool fast = false;
+        if (i < G.g)
+            fast = load_any(buf, i, m);
+        while (i < G.g) {
+            const uint32_t nx = i + step;
+            const bool staged = fast && !a.xch_shift;
+            uint64_t pb = 0;
+            uint32_t c = 0;
+            if (staged)
+                pb = x.stage_exchange(buf, tile);
+            else
+                c = fast ? x.template exchange<true>(buf, i, m, xt, a.xch_shift, written)
+                         : x.template exchange<false>(buf, i, m, xt, a.xch_shift, written);
+            // one place that loads the next group, so the loaded registers are
+            // never copied (a copy would wait for the loads)
+            bool nfast = false;
+            if (nx < G.g)
+                nfast = load_any(buf, nx, m);
+            if (staged)
+                c = x.finish_exchange(pb, i, tile, xt, written);
+            fold(c, i);
+            x.bar();  // the counts, the tables and the tile are rewritten by the next group
+            i = nx;
+            fast = nfast;
+        }
+        if (tid == 0) {
+            a.out[2 * bid] = vmin;
+            a.out[2 * bid + 1] = vmax;
+            if (FIRST && a.split_out && bid == 0 && G.g == 1)
+                *a.split_out = vmin;
+            if (a.written && written)
+                atomicAdd(reinterpret_cast<unsigned long long *>(a.written), (unsigned long long)written);
+        }
+        return;
+    }
+
     // One register buffer: the next group's loads are issued right after this
     // group's stores (staged form: right after the tile is complete, ahead of
     // the tile's write-back), before the barrier that lets the counts be
     // rewritten.
-    const uint32_t step = gridDim.x;
     v4u buf[NV];
     Mask m;
-    uint32_t i = bid;
     bool fast = false;
     if (i < G.g)
         fast = load_any(buf, i, m);
@@ -233,7 +293,9 @@ const void *level_rs_fn_t(bool first)
 template <typename T, int NT, int NV, int FORM>
 constexpr size_t level_rs_lds()
 {
-    return FORM == kFormExchange ? LevelCtx<T, NT, NV>::XCH_BYTES
+    return FORM == kFormExchange ? (xch_prefetch<T, NT, NV, FORM>()
+                                        ? 2 * LevelCtx<T, NT, NV>::XCH_BYTES + (size_t)NT * NV * 16
+                                        : LevelCtx<T, NT, NV>::XCH_BYTES)
            : FORM == kFormStaged ? (size_t)LevelCtx<T, NT, NV>::NVEC * 16
                                  : 0;
 }

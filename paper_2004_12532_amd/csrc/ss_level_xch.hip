@@ -16,6 +16,8 @@ namespace ss {
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint32_t)
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, uint64_t)
 SS_RS_VARIANTS(SS_INSTANTIATE_XCH, KV)
+SS_INSTANTIATE_XCH(uint64_t, 512, 4)
+SS_INSTANTIATE_XCH(KV, 512, 4)
 
 }  // namespace ss
 

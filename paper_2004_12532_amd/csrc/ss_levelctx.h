@@ -12,7 +12,10 @@
 
 namespace ss {
 
-template <typename T, int NT, int NV>
+// LDSBAR: the workgroup barriers of the body wait only for LDS accesses, so
+// the next group's loads, issued before the staged exchange ranks and swaps
+// the current group, stay in flight across them.
+template <typename T, int NT, int NV, bool LDSBAR = false>
 struct LevelCtx {
     static constexpr int W = sizeof(T);
     static constexpr int LOG2W = W == 4 ? 2 : W == 8 ? 3 : 4;
@@ -30,6 +33,14 @@ struct LevelCtx {
     uint32_t g, s;
     uint32_t log2b, vpl_log2, nvec;
     int tid, lane, wid;
+
+    __device__ __forceinline__ void bar() const
+    {
+        if constexpr (LDSBAR)
+            lds_barrier();
+        else
+            __syncthreads();
+    }
 
     __device__ __forceinline__ uint32_t line_of(uint32_t j, uint32_t i) const
     {
@@ -128,7 +139,7 @@ struct LevelCtx {
             if (lane == 0)
                 cnt[r * NW + wid] = tot;
         }
-        __syncthreads();
+        bar();
         if (wid == 0) {
             constexpr int C = (E + 63) / 64;
             uint32_t x[C], sum = 0;
@@ -156,7 +167,7 @@ struct LevelCtx {
             if (lane == 63)
                 cnt[E] = inc;
         }
-        __syncthreads();
+        bar();
         return pb;
     }
 
@@ -265,6 +276,110 @@ struct LevelCtx {
     static constexpr int XCH_SLOTS = NVEC * V / 2;
     static constexpr size_t XCH_BYTES = XCH_SLOTS * sizeof(uint16_t);
 
+    // The write-minimal exchange of a group whose slots are all real (the fast
+    // path), staged through an LDS tile of the group's vectors (vector q at
+    // tile[q]), in three phases and three barriers, the last at the end of
+    // the group in the caller.
+    //  (a) stage_exchange: each thread evaluates its slots and writes its
+    //      vectors to the tile; lane 0 of each wavefront posts the predecessor
+    //      count of each of its (round, wavefront) blocks, which lie in slot
+    //      order.  The caller then issues the next group's loads into the
+    //      registers the group leaves free.
+    //  (b) finish_exchange: every wavefront scans the block counts itself (c_i
+    //      and the blocks' offsets), ranks the misplaced elements of its
+    //      blocks and writes two tables: the k-th successor from the front
+    //      below c_i at xt[k], the k-th predecessor from the back at or after
+    //      c_i at xt[S/2 + k].  Blocks with neither kind are skipped on a
+    //      wavefront-uniform test.  The wavefront holding slot c_i posts its
+    //      rank, so m_i = c_i - rank.
+    //  (c) Thread t < m_i swaps pair t: both values come from the tile, and
+    //      each is stored at the other's slot.
+    // These are the pairs of the serial two-pointer scan, as in exchange()
+    // below.  Slot numbers read back from the tables are clamped to the group,
+    // so no store leaves the group's lines whatever the tables hold.  xt holds
+    // S 16-bit slot numbers.
+    __device__ __forceinline__ uint64_t stage_exchange(const v4u (&buf)[NV], v4u *tile) const
+    {
+        const Mask all{~0ull, 0ull};
+        uint64_t pb = 0;
+#pragma unroll
+        for (int r = 0; r < NV; r++) {
+            const uint32_t bits = bits_of<true>(buf[r], r, all);
+            pb |= (uint64_t)bits << (r * V);
+            uint32_t tot = 0;
+#pragma unroll
+            for (int e = 0; e < V; e++)
+                tot += __popcll(__ballot((bits >> e) & 1));
+            if (lane == 0)
+                cnt[r * NW + wid] = tot;
+            tile[r * NT + tid] = buf[r];
+        }
+        return pb;
+    }
+
+    // Phases (b) and (c) for the group staged by stage_exchange, whose decider
+    // bits are pb.  Returns c_i.
+    __device__ __forceinline__ uint32_t finish_exchange(uint64_t pb, uint32_t i, const v4u *tile, uint16_t *xt,
+                                                        uint64_t &written) const
+    {
+        static_assert(E <= 64, "one wavefront scans the block counts");
+        constexpr uint32_t VM = (1u << V) - 1;
+        constexpr uint32_t S = NVEC * V;
+        constexpr uint32_t HALF = S / 2;
+        static_assert((HALF & (HALF - 1)) == 0, "table index masks");
+        bar();
+        // (b)
+        const uint32_t bc = lane < E ? cnt[lane] : 0u;
+        const uint32_t inc = wave_scan_incl(bc, lane);
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        const uint32_t excl = inc - bc;
+        uint16_t *const bt = xt + HALF;
+#pragma unroll 1
+        for (int r = 0; r < NV; r++) {
+            const uint32_t blk = r * NW + wid;
+            const uint32_t s_lo = blk * 64 * V;  // the block's first slot
+            const uint32_t bits = (uint32_t)(pb >> (r * V)) & VM;
+            const uint32_t s0 = s_lo + lane * V;
+            uint32_t wf = 0, wb = 0;
+#pragma unroll
+            for (int e = 0; e < V; e++) {
+                const bool p = (bits >> e) & 1, below = s0 + e < c;
+                wf |= (uint32_t)(!p && below) << e;
+                wb |= (uint32_t)(p && !below) << e;
+            }
+            const bool holds_c = s_lo <= c && c < s_lo + 64 * V;
+            if (!holds_c && __ballot((wf | wb) != 0) == 0)
+                continue;
+            uint32_t rp = (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)blk);
+#pragma unroll
+            for (int k = 0; k < V; k++)
+                rp += lanes_below(__ballot((bits >> k) & 1));
+            if (holds_c && s0 <= c && c < s0 + V)
+                cnt[E] = rp + __popc(bits & ((1u << (c - s0)) - 1));
+#pragma unroll
+            for (int e = 0; e < V; e++) {
+                if ((wf >> e) & 1)
+                    xt[(s0 + e - rp) & (HALF - 1)] = (uint16_t)(s0 + e);
+                if ((wb >> e) & 1)
+                    bt[(c - rp - 1) & (HALF - 1)] = (uint16_t)(s0 + e);
+                rp += (bits >> e) & 1;
+            }
+        }
+        bar();
+        // (c)
+        uint32_t m = c < S ? c - cnt[E] : 0u;
+        m = m < HALF ? m : HALF;
+        written += 2ull * m;
+        for (uint32_t t = tid; t < m; t += NT) {
+            uint32_t xs = xt[t], ys = bt[t];
+            xs = xs < S ? xs : S - 1;
+            ys = ys < S ? ys : S - 1;
+            Elem<T>::store1(tile[ys / V], (int)(ys % V), slot_ptr(xs, i));
+            Elem<T>::store1(tile[xs / V], (int)(xs % V), slot_ptr(ys, i));
+        }
+        return c;
+    }
+
     // Write-minimal partition of group i (the two-pointer exchange of the
     // serial step, Section 4): the k-th successor from the front of the slot
     // order that lies in [0, c_i) swaps with the k-th predecessor from the
@@ -283,6 +398,8 @@ struct LevelCtx {
     // anyway and the exchange's extra passes cost more than they save.
     // shift = 0 exchanges every group.  `written` grows by the elements the
     // group stores (2 m_i, or its slot count when stored stably).  Returns c_i.
+    // With the group's vectors in an LDS tile (tile not null) the swaps are
+    // made by xchg_tile.
     template <bool FAST>
     __device__ __forceinline__ uint32_t exchange(const v4u (&buf)[NV], uint32_t i, const Mask &m,
                                                  uint16_t *xt, uint32_t shift, uint64_t &written) const
@@ -303,7 +420,7 @@ struct LevelCtx {
                 if ((uint32_t)lane == t % 64)
                     cnt[E + 1] = rp + __popc(bits & ((1u << e) - 1));
             }
-            __syncthreads();
+            bar();
             mis = c - cnt[E + 1];
         }
         if (shift && (mis << shift) > S) {
@@ -319,7 +436,7 @@ struct LevelCtx {
             if (!p && slot < c)
                 xt[slot - rp] = (uint16_t)slot;
         });
-        __syncthreads();
+        bar();
         // (2) each misplaced predecessor takes its partner's slot, stores
         // itself there and posts its own slot in exchange
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
@@ -329,7 +446,7 @@ struct LevelCtx {
                 xt[k] = (uint16_t)slot;
             }
         });
-        __syncthreads();
+        bar();
         // (3) each misplaced successor stores itself at its partner's slot
         for_ranks(pb, [&](int r, int e, uint32_t slot, bool p, uint32_t rp) {
             if (!p && slot < c)
