@@ -146,8 +146,8 @@ enum ss_status {
  * 16 bytes, with default engine, b and tile_bytes, chooses the form of its
  * first level from a sample of 4096 keys at fixed positions (64 runs of 64 keys
  * spread evenly over the array).  It takes the exchange form with 32768-byte
- * groups when at most 1/16 (8-byte keys) or 1/10 (16-byte records) of the
- * sample, or at least 15/16 or 9/10, are predecessors; else the stable form.
+ * groups when at most 1/16 (8-byte keys) or 1/9 (16-byte records) of the
+ * sample, or at least 15/16 or 8/9, are predecessors; else the stable form.
  * The choice depends only on the input, so a call stays deterministic;
  * ss_stats.exchange_levels reports it. */
 
